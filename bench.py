@@ -1,0 +1,244 @@
+"""Benchmark: the Hermite block step of a Plummer sphere, N = 65536, on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+One timed step is one pass of the whole hot path over the system: block
+selection, prediction of all particles, the force/jerk/potential sweep of
+the active block, and the corrector with the next Aarseth step.  Before each
+step every particle's step size is reset to one shared step h = 2^-12, so
+the active block is all N particles and every step does N^2 interactions
+(the paper's full-N workload; Section 5).  Positions keep advancing.
+
+Metric: interactions/s (N_act * N per step) and GFLOPS at the paper's 60
+flops per interaction, for the mixed path (headline) and the FP64 path.
+The roofline entry is for the sweep kernel (the dominant kernel), with its
+average duration measured by HIP events on the launch stream, priced at 42
+algorithmic flops per interaction (count of the operations in the force,
+jerk and potential equations, FMA = 2).  The cpu_baseline entry times the
+FP64 CPU oracle on a bounded sample of active particles of the same state.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 65536
+SEED = 3
+ETA = 0.02
+TB = 20
+H_SHARED_K = 12                      # shared step 2^-12 for the timed steps
+FLOPS_PAPER = 60                     # per interaction, the paper's convention
+FLOPS_ALGO = 42                      # per interaction, operation count
+PEAK_FP64 = 78.6e12                  # MI355X vector FP64, FLOP/s
+PEAK_FP32 = 157.3e12                 # MI355X vector FP32 (packed), FLOP/s
+PEAK_FP32_UNPACKED = 78.6e12         # FP32 as issued by this build
+METRIC = ("force+jerk interactions/s & GFLOPS (N=65536); mixed vs FP64 at "
+          "≤1e-6 rel err")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sweep's sharding is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_calib:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": 256 << 20, "reps": 5}))
+        return
+    from paper_1104_2700_amd import hermite as H, inputs
+
+    x, v, m = inputs.plummer(N, SEED)
+    eps2 = (4.0 / N) ** 2
+    ctx = H.Context(0)
+    params = H.dt_params(ETA, H.DT_PAPER, 3, 20)
+    base = H.State(x, v, m, TB)
+    ctx.initialize(base, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    h_ticks = 1 << (TB - H_SHARED_K)
+    stream = torch.cuda.current_stream()
+
+    results = {}
+    precs = [p for p in args.precisions.split(",") if p]
+    for pname in precs:
+        prec = H.PRECISIONS[pname]
+        if not args.no_autotune:
+            # pick the sweep's launch shape for this size (untimed set-up)
+            ts = base.clone()
+            ts.xp.copy_(ts.x)
+            ts.vp.copy_(ts.v)
+            ctx.autotune(ts, eps2, prec, N)
+            del ts
+        tuning = ctx.get_tuning(prec).as_dict()
+        s = base.clone()
+        s.dt.fill_(h_ticks)
+
+        def one_step():
+            s.dt.fill_(h_ticks)
+            ctx.step(s, eps2, params, prec, use_graph=not args.no_graph)
+
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cnt = ctx.counters()
+        assert cnt["n_act"] == N, cnt
+        ms_step = 1e3 * wall / args.steps
+        inter_s = N * N / (wall / args.steps)
+        # kernel-level timing of the sweep (plan + sweep + reduce) with HIP
+        # events on the launch stream, at the same launch shape
+        fs = base.clone()
+        fs.xp.copy_(fs.x)
+        fs.vp.copy_(fs.v)
+        acc, jrk, pot = ctx.force_jerk(fs, None, eps2, prec)
+        reps = max(10, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.force_jerk(fs, None, eps2, prec, acc=acc, jerk=jrk, pot=pot)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        k_ms = e0.elapsed_time(e1) / reps
+        results[pname] = {
+            "ms_per_step": ms_step, "interactions_per_s": inter_s,
+            "gflops_60": inter_s * FLOPS_PAPER / 1e9,
+            "sweep_ms": k_ms,
+            "sweep_interactions_per_s": N * N / (k_ms * 1e-3),
+            "tuning": tuning,
+            "out": (acc.cpu().numpy(), jrk.cpu().numpy(), pot.cpu().numpy()),
+        }
+
+    cpu = None
+    accuracy = {}
+    if not args.no_cpu:
+        cpu, accuracy = cpu_leg(x, v, m, eps2, results, args.cpu_seconds)
+
+    head = "mixed" if "mixed" in results else precs[0]
+    r = results[head]
+    achieved = FLOPS_ALGO * N * N / (r["sweep_ms"] * 1e-3)
+    peak = PEAK_FP32 if head != "fp64" else PEAK_FP64
+    out = {
+        "metric": METRIC,
+        "value": r["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32 mixed" if head != "fp64" else "f64",
+        "data": "synthetic Plummer sphere (Henon units), N=65536, seed 3",
+        "config": {"workload": "plummer_n65536_full_block_step", "n": N, "n_act": N,
+                   "eps": 4.0 / N, "eta": ETA, "precision": head,
+                   "shared_step": 2.0 ** -H_SHARED_K,
+                   "graph": not args.no_graph},
+        "gflops_60": r["gflops_60"],
+        "paths": {p: {k: v for k, v in q.items() if k != "out"} for p, q in results.items()},
+        "accuracy_vs_oracle": accuracy,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "sweep (plan+sweep+reduce), precision %s" % head,
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "flops_per_interaction": FLOPS_ALGO,
+            "frac_vs_fp64_or_unpacked_fp32_peak": achieved / PEAK_FP64,
+        },
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in results and head != "fp64":
+        f = results["fp64"]
+        out["fp64_vs_mixed"] = {
+            "fp64_interactions_per_s": f["interactions_per_s"],
+            "mixed_speedup_step": r["interactions_per_s"] / f["interactions_per_s"],
+            "mixed_speedup_sweep": f["sweep_ms"] / r["sweep_ms"],
+            "fp64_sweep_frac_fp64_peak": FLOPS_ALGO * N * N / (f["sweep_ms"] * 1e-3) / PEAK_FP64,
+        }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_leg(x, v, m, eps2, results, target_s):
+    """Times the FP64 oracle on a sample of active particles of the same
+    state, on every host core it is given, and measures the GPU outputs'
+    error against it on the 1024-particle evaluation sample."""
+    from oracle import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    eval_idx = np.sort(np.random.default_rng(1003).choice(N, 1024, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    ra, rj, rp = O.force(x, v, m, eval_idx, eps2)
+    t1 = time.perf_counter()
+    rate0 = 1024 * N / (t1 - t0)
+    extra = int(min(N - 1024, max(0, rate0 * target_s / N - 1024)))
+    rng = np.random.default_rng(7)
+    rest = np.setdiff1d(np.arange(N, dtype=np.int32), eval_idx)
+    more = np.sort(rng.choice(rest, size=extra, replace=False)).astype(np.int32)
+    t2 = time.perf_counter()
+    if extra:
+        O.force(x, v, m, more, eps2)
+    t3 = time.perf_counter()
+    n_i = 1024 + extra
+    secs = (t1 - t0) + (t3 - t2)
+    cpu = {"value": n_i * N / secs, "unit": "interactions/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "%d active particles x %d j of the N=65536 Plummer state "
+                     "(FP64, Neumaier sums), %.1f s" % (n_i, N, secs)}
+    acc = {}
+    for p, r in results.items():
+        A, J, P = r["out"]
+        ea = np.linalg.norm(A[:, eval_idx] - ra, axis=0) / np.linalg.norm(ra, axis=0)
+        ej = np.linalg.norm(J[:, eval_idx] - rj, axis=0) / np.linalg.norm(rj, axis=0)
+        ep = np.abs(P[eval_idx] - rp) / np.abs(rp)
+        acc[p] = {"sample": 1024,
+                  "acc_rel_median": float(np.median(ea)), "acc_rel_max": float(ea.max()),
+                  "jerk_rel_median": float(np.median(ej)), "jerk_rel_p99": float(np.percentile(ej, 99)),
+                  "jerk_rel_max": float(ej.max()), "jerk_n_above_1e-6": int((ej > 1e-6).sum()),
+                  "pot_rel_median": float(np.median(ep)), "pot_rel_max": float(ep.max())}
+    return cpu, acc
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,261 @@
+/*
+ * hermite.h -- C ABI of libhermite, an MI355X (gfx950) implementation of the
+ * hot path of the fourth-order Hermite N-body scheme with block
+ * (power-of-two individual) timesteps of Tanikawa, Yoshikawa, Okamoto &
+ * Nitadori (arXiv:1104.2700):
+ *
+ *   select the block  ->  predict  ->  force/jerk/potential sweep  ->
+ *   correct + new timestep        (Section 2, procedure steps 1-8)
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Every function returns int: HERMITE_OK (0) or a negative error code;
+ *    hermite_last_error() then returns a thread-local message.  Nothing
+ *    throws across the ABI.
+ *  - "device" pointers are HIP device memory (e.g. torch tensors on cuda:0,
+ *    data_ptr()), owned by the caller.  The library never frees them.  The
+ *    library owns only its context scratch (allocated on first need and
+ *    freed by hermite_destroy).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue work and return without synchronising, unless stated.
+ *    Errors of kernels that run later surface at the next synchronising
+ *    call (hermite_sync, hermite_counters, hermite_run).
+ *  - Vector fields are SoA: a pointer to 3*n doubles laid out [3][n]
+ *    (all x, then all y, then all z).  Compact per-active outputs are
+ *    [3][stride] with stride = n_act_max.
+ *  - Times are int64 ticks of 2^-tick_bits; the global time unit is 1.
+ *  - G = 1 (standard N-body units, Section 4).
+ *  - Index lists are int32, ascending, without duplicates.  Violations are
+ *    undefined behaviour (not checked on the device).
+ *  - A context is not thread-safe: use one per host thread.
+ */
+#ifndef HERMITE_H
+#define HERMITE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define HERMITE_OK          0
+#define HERMITE_EINVAL     -1  /* bad argument (null, size, range, NaN)   */
+#define HERMITE_ENODEV     -2  /* no such HIP device                      */
+#define HERMITE_EHIP       -3  /* a HIP runtime call failed (message set) */
+#define HERMITE_ENOMEM     -4  /* scratch allocation failed               */
+#define HERMITE_ENONFINITE -5  /* non-finite force/jerk detected          */
+#define HERMITE_ENOTSUP    -6  /* combination not supported               */
+
+/* ---- precision of the force/jerk sweep -------------------------------- */
+/* FP64 everywhere.                                                        */
+#define HERMITE_FP64      0
+/* Section 3.2 precision split, modified: relative position and velocity  */
+/* subtracted in FP64, cast to FP32 for the pair arithmetic (r^2 + eps^2, */
+/* rsqrt, jerk and potential terms), partial sums over short runs of j in */
+/* FP32 and the running sums of acc, jerk and pot in FP64.                */
+#define HERMITE_MIXED     1
+/* As HERMITE_MIXED, but the running sums are two-float (FP32 hi + lo,    */
+/* compensated by TwoSum) instead of FP64.                                */
+#define HERMITE_MIXED_2F  2
+
+/* ---- timestep criterion forms (Section 2, eq. (timestep)) ------------ */
+#define HERMITE_DT_PAPER    0  /* dt = eta * sqrt(R), as printed          */
+#define HERMITE_DT_AARSETH  1  /* dt = sqrt(eta * R), the classic form    */
+
+/* Particle state.  All pointers are device pointers, caller-owned.
+ * tick_bits in [1, 52]; k_max of the timestep parameters <= tick_bits. */
+typedef struct hermite_state {
+    int64_t n;            /* number of particles, 1 <= n <= INT32_MAX     */
+    int32_t tick_bits;    /* time tick = 2^-tick_bits                     */
+    int32_t reserved0;
+    const double* m;      /* [n] masses                                   */
+    double* x;            /* [3][n] positions at t_i                      */
+    double* v;            /* [3][n] velocities at t_i                     */
+    double* a;            /* [3][n] accelerations a0 at t_i               */
+    double* j;            /* [3][n] jerks j0 at t_i                       */
+    double* xp;           /* [3][n] predicted positions (written)         */
+    double* vp;           /* [3][n] predicted velocities (written)        */
+    double* pot;          /* [n] potential at t_i (written by correct)    */
+    int64_t* t;           /* [n] last time of each particle, in ticks     */
+    int64_t* dt;          /* [n] current step of each particle, in ticks  */
+} hermite_state;
+
+/* Aarseth criterion and quantisation (Section 2, eq. (timestep) and the
+ * hierarchical power-of-two scheme).  Steps are 2^-k, k in [k_min, k_max],
+ * at most double the previous step, commensurate with the block time. */
+typedef struct hermite_dt_params {
+    double  eta;          /* accuracy parameter, > 0                      */
+    int32_t form;         /* HERMITE_DT_PAPER or HERMITE_DT_AARSETH       */
+    int32_t k_min;        /* largest step 2^-k_min, k_min >= 0            */
+    int32_t k_max;        /* smallest step 2^-k_max, k_max <= tick_bits   */
+    int32_t reserved0;
+} hermite_dt_params;
+
+/* Independent clusters in one state (ensembles).  Particles of cluster c
+ * occupy [offsets[c], offsets[c+1]); a particle feels only its own
+ * cluster, softened by eps2[c].  Both arrays are device memory.  NULL in
+ * place of a hermite_clusters* means one system of all n particles. */
+typedef struct hermite_clusters {
+    int32_t n_clusters;       /* C >= 1                                   */
+    int32_t reserved0;
+    int64_t max_size;         /* host value: max_c (offsets[c+1]-offsets[c]) */
+    const int64_t* offsets;   /* [C+1], offsets[0] = 0, offsets[C] = n,   */
+                              /* strictly increasing                      */
+    const double* eps2;       /* [C] squared softening per cluster        */
+} hermite_clusters;
+
+/* Launch shape of the sweep; see hermite_autotune. */
+typedef struct hermite_tuning {
+    int32_t target_lanes;     /* lanes the j-split aims to keep busy      */
+    int32_t wg_per_cu;        /* persistent workgroups per compute unit   */
+    int32_t min_j_per_lane;   /* smallest j-run a lane is given per chunk */
+    int32_t variant;          /* inner-loop variant (0 = default)         */
+} hermite_tuning;
+
+typedef struct hermite_ctx hermite_ctx;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (makes it current).
+ * ENODEV if the device does not exist. */
+int hermite_create(int device, hermite_ctx** out);
+
+/* Free the context's scratch, graphs and streams.  NULL is a no-op. */
+int hermite_destroy(hermite_ctx* ctx);
+
+/* Thread-local message of the last error (never NULL). */
+const char* hermite_last_error(void);
+
+/* Block until all work the library enqueued on `stream` has finished;
+ * reports errors of earlier kernels (EHIP). */
+int hermite_sync(hermite_ctx* ctx, void* stream);
+
+/* ---- the hot path -------------------------------------------------------- */
+
+/* Procedure step 1 (Section 2): T = min_i (t_i + dt_i), the active list
+ * {i : t_i + dt_i == T} in ascending order.  Outputs stay on the device:
+ * idx_out [n] (first n_act entries valid), *n_act_dev, *T_dev.  If
+ * T > T_end, *n_act_dev = 0 (nothing to do) and *T_dev still holds T.
+ * Pass T_end = INT64_MAX for no limit. */
+int hermite_select_block(hermite_ctx* ctx, const hermite_state* s,
+                         int32_t* idx_out, int32_t* n_act_dev, int64_t* T_dev,
+                         int64_t T_end, void* stream);
+
+/* Procedure steps 2-3, equations (xpred), (vpred): for every particle,
+ * with dt_i = (T - t_i) ticks, writes s->xp, s->vp.  T is read from
+ * T_dev (device) when non-NULL, else T_host is used.  If n_act_dev is
+ * non-NULL and *n_act_dev == 0 the kernel does nothing. */
+int hermite_predict(hermite_ctx* ctx, const hermite_state* s,
+                    const int64_t* T_dev, int64_t T_host,
+                    const int32_t* n_act_dev, void* stream);
+
+/* Procedure step 4, equations (acc), (jrk), (pot): for each active i in
+ * idx[0..n_act), sums over every j != i of its system (all n, or its
+ * cluster) at the predicted state s->xp, s->vp with softening eps2 (or
+ * cl->eps2[c]):
+ *     acc  += m_j r / s^{3/2}
+ *     jerk += m_j / s^{3/2} (v - 3 (r.v)/s r)
+ *     pot  -= m_j / s^{1/2}
+ * with r = xp_j - xp_i, v = vp_j - vp_i, s = r^2 + eps2.
+ * idx: device [n_act_max], or NULL for the identity (requires
+ * n_act_max == n).  n_act_dev: device count, or NULL for n_act_max.
+ * Outputs (device): acc [3][n_act_max], jerk [3][n_act_max],
+ * pot [n_act_max] (may be NULL); only the first n_act columns written.
+ * precision: HERMITE_FP64 / HERMITE_MIXED / HERMITE_MIXED_2F.
+ * Results are bitwise reproducible run to run for a fixed tuning. */
+int hermite_force_jerk(hermite_ctx* ctx, const hermite_state* s,
+                       const hermite_clusters* cl,
+                       const int32_t* idx, const int32_t* n_act_dev,
+                       int32_t n_act_max, double eps2, int precision,
+                       double* acc, double* jerk, double* pot, void* stream);
+
+/* Procedure steps 5-8 with the snap/crackle, corrector and timestep
+ * equations of Section 2: for each active i (idx, n_act as above, T as
+ * in hermite_predict), from s->xp, s->vp, the old s->a, s->j and the new
+ * compact acc, jerk, pot: corrects s->x, s->v, sets s->a, s->j, s->pot,
+ * t_i = T and the next dt_i (criterion at the new time with
+ * s1 = s0 + c0 dt, c1 = c0).  crit_out (device [n_act_max], may be NULL)
+ * receives the criterion before quantisation. */
+int hermite_correct(hermite_ctx* ctx, const hermite_state* s,
+                    const int32_t* idx, const int32_t* n_act_dev,
+                    int32_t n_act_max, const int64_t* T_dev, int64_t T_host,
+                    const double* acc, const double* jerk, const double* pot,
+                    const hermite_dt_params* p, double* crit_out,
+                    void* stream);
+
+/* First step sizes (no snap or crackle yet): dt0 = eta_f |a| / |j| with
+ * eta_f = eta (paper form) or sqrt(eta) (classic form), quantised at
+ * T = 0; sets t_i = 0.  Reads s->a, s->j. */
+int hermite_init_dt(hermite_ctx* ctx, const hermite_state* s,
+                    const hermite_dt_params* p, void* stream);
+
+/* t = 0 set-up: a full sweep at the current x, v (copied to xp, vp)
+ * gives a0, j0 and pot, then hermite_init_dt. */
+int hermite_initialize(hermite_ctx* ctx, const hermite_state* s,
+                       const hermite_clusters* cl, double eps2,
+                       int precision, const hermite_dt_params* p,
+                       void* stream);
+
+/* Energy check (Section 2 after eq. (pot); Section 4): K = 1/2 sum m v^2
+ * and W = 1/2 sum m phi, phi from a separate FP64 potential sweep at the
+ * positions s->x.  out_dev (device) receives [K, W] per cluster
+ * ([C][2]; [2] for a single system).  Deterministic. */
+int hermite_energy(hermite_ctx* ctx, const hermite_state* s,
+                   const hermite_clusters* cl, double eps2, double* out_dev,
+                   void* stream);
+
+/* ---- whole steps, graphs and runs -------------------------------------- */
+
+/* One block step: select -> predict -> force -> correct, with T and n_act
+ * kept on the device (context scratch).  With use_graph != 0 the four
+ * stages are captured once into a HIP graph (per state/cluster/precision/
+ * parameter set) and replayed.  Steps past T_end do nothing. */
+int hermite_step(hermite_ctx* ctx, const hermite_state* s,
+                 const hermite_clusters* cl, double eps2, int precision,
+                 const hermite_dt_params* p, int64_t T_end, int use_graph,
+                 void* stream);
+
+/* Repeat hermite_step until every particle reaches T_end (ticks; must be
+ * a multiple of 2^(tick_bits - k_min)).  The host reads the device block
+ * time once every sync_every steps.  steps_out / interactions_out (host,
+ * may be NULL) receive the block-step count and the number of pair
+ * interactions (sum over steps of sum_i n_c(i)) of this call. */
+int hermite_run(hermite_ctx* ctx, const hermite_state* s,
+                const hermite_clusters* cl, double eps2, int precision,
+                const hermite_dt_params* p, int64_t T_end, int use_graph,
+                int32_t sync_every, int64_t* steps_out,
+                int64_t* interactions_out, void* stream);
+
+/* Cumulative device counters since creation (synchronises `stream`):
+ * out[0] block steps, out[1] interactions, out[2] clamped steps,
+ * out[3] last block time T, out[4] last n_act. */
+int hermite_counters(hermite_ctx* ctx, int64_t out[5], void* stream);
+
+/* ---- launch shape and autotuner ------------------------------------------ */
+
+int hermite_get_tuning(hermite_ctx* ctx, int precision, hermite_tuning* out);
+int hermite_set_tuning(hermite_ctx* ctx, int precision,
+                       const hermite_tuning* in);
+
+/* Time candidate launch shapes of the sweep for this state, precision and
+ * active count (the first n_act particles, or all for n_act = n) with HIP
+ * events, keep the fastest whose results agree with the default shape
+ * (FP64: 1e-13 relative, mixed: 1e-6), install it in the context and,
+ * if cache_path is non-NULL, merge it into that JSON file keyed by
+ * device architecture, precision and size bucket.  Synchronises. */
+int hermite_autotune(hermite_ctx* ctx, const hermite_state* s,
+                     double eps2, int precision, int32_t n_act,
+                     const char* cache_path, void* stream);
+
+/* Load tunings from a cache written by hermite_autotune for this device
+ * and the given n / n_act bucket; returns HERMITE_OK if an entry was
+ * found and installed, HERMITE_EINVAL if none matched. */
+int hermite_load_tuning(hermite_ctx* ctx, const char* cache_path,
+                        int precision, int64_t n, int32_t n_act);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HERMITE_H */

@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP translation units of libhermite.
+// Not part of the public ABI (include/hermite.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hm {
+
+// Workgroup size of the sweep (four wave64s) and the number of j-particles
+// staged through LDS per tile (one per thread).
+constexpr int kWG = 256;
+constexpr int kTJ = 256;
+
+// Shape of one force sweep, decided on the device from the active count
+// (so that a captured graph adapts to every block size).
+struct SweepPlan {
+    int32_t n_act;        // active particles this call
+    int32_t L;            // lanes cooperating on one active particle
+    int32_t ti;           // active particles per work item (kWG / L)
+    int32_t s_max;        // largest number of j-chunks of any cluster
+    int64_t jc;           // j-chunk length (multiple of kTJ)
+    int32_t total_items;  // work items (cluster, i-tile, j-chunk)
+    uint32_t next_item;   // dynamic work counter of the persistent grid
+};
+
+// Everything the plan, sweep and reduce kernels read.  Passed by value.
+struct SweepArgs {
+    const double* xp;          // [3][n] positions of i and j
+    const double* vp;          // [3][n] velocities of i and j
+    const double* m;           // [n]
+    int64_t n;
+    const int32_t* idx;        // [n_act_max] or null (identity)
+    const int32_t* n_act_dev;  // or null (n_act_max)
+    int32_t n_act_max;
+    int32_t n_clusters;        // >= 1
+    const int64_t* offsets;    // [C+1] or null when C == 1
+    const double* eps2_c;      // [C] or null when C == 1
+    double eps2;               // used when eps2_c is null
+    int64_t n_cmax;            // largest cluster size
+    // plan and per-cluster scratch (device)
+    SweepPlan* plan;
+    int32_t* act_start;        // [C]
+    int32_t* act_cnt;          // [C]
+    int32_t* chunks;           // [C]
+    int32_t* item_off;         // [C+1]
+    double* partial;           // [s_max][7][n_act]
+    int64_t partial_cap;       // doubles available in partial
+    // tuning
+    int32_t target_lanes;
+    int32_t min_j_per_lane;
+    int32_t ipl;               // active particles per lane (set by launch_force)
+    // counters (may be null): [0] steps, [1] interactions, [4] last n_act
+    int64_t* counters;
+    // outputs of the reduce stage
+    double* acc;               // [3][n_act_max]
+    double* jerk;              // [3][n_act_max] or null
+    double* pot;               // [n_act_max] or null
+};
+
+// Sweep launchers (sweep.hip).  precision: 0 fp64, 1 mixed, 2 mixed-2f.
+// variant: 0 one active particle per lane, 1 two per lane.
+// pot_only: the energy sweep (FP64, potential only).
+hipError_t launch_force(const SweepArgs& a, int precision, int variant,
+                        int grid, bool pot_only, hipStream_t st);
+
+// Block selection (integrate.hip).
+// Number of select blocks (size of block_min / block_cnt) for n particles.
+int select_blocks(int64_t n);
+
+hipError_t launch_select(int64_t n, const int64_t* t, const int64_t* dt,
+                         int64_t T_end, int32_t* idx, int32_t* n_act,
+                         int64_t* T, int64_t* block_min, int32_t* block_cnt,
+                         int64_t* counters, hipStream_t st);
+
+hipError_t launch_predict(int64_t n, int tick_bits, const double* x,
+                          const double* v, const double* a, const double* j,
+                          const int64_t* t, const int64_t* T_dev,
+                          int64_t T_host, const int32_t* n_act_dev,
+                          double* xp, double* vp, hipStream_t st);
+
+struct CorrectArgs {
+    int64_t n;
+    int tick_bits;
+    const int32_t* idx;
+    const int32_t* n_act_dev;
+    int32_t n_act_max;
+    const int64_t* T_dev;
+    int64_t T_host;
+    const double* xp;
+    const double* vp;
+    const double* acc1;        // [3][n_act_max]
+    const double* jrk1;        // [3][n_act_max]
+    const double* pot1;        // [n_act_max] or null
+    double* x;
+    double* v;
+    double* a;
+    double* j;
+    double* pot;
+    int64_t* t;
+    int64_t* dt;
+    double eta;
+    int form;
+    int k_min;
+    int k_max;
+    double* crit_out;          // or null
+    int64_t* counters;         // [2] += clamped, or null
+};
+
+hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
+
+hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,
+                          const double* j, int64_t* t, int64_t* dt,
+                          double eta, int form, int k_min, int k_max,
+                          int64_t* counters, hipStream_t st);
+
+hipError_t launch_copy2(int64_t count, const double* src0, double* dst0,
+                        const double* src1, double* dst1, hipStream_t st);
+
+hipError_t launch_iota(int32_t count, int32_t* out, hipStream_t st);
+
+int sweep_occupancy(int precision, int variant, bool pot_only);
+
+hipError_t launch_energy_reduce(int64_t n, int n_clusters,
+                                const int64_t* offsets, const double* m,
+                                const double* v, const double* phi,
+                                double* out, hipStream_t st);
+
+}  // namespace hm

@@ -1,0 +1,880 @@
+// Host side of libhermite: the C ABI of include/hermite.h, argument
+// validation, context scratch, HIP graph capture/replay and the autotuner.
+#include "hermite.h"
+#include "hermite_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace hm;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return fail(HERMITE_EHIP, "%s: %s (%s:%d)", #call,                \
+                        hipGetErrorString(e_), __FILE__, __LINE__);           \
+    } while (0)
+
+#define CHECK(code)                                                           \
+    do {                                                                      \
+        int c_ = (code);                                                      \
+        if (c_ != HERMITE_OK) return c_;                                      \
+    } while (0)
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GraphEntry {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct hermite_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string arch;
+    hipStream_t cap_stream = nullptr;
+    hermite_tuning tuning[3];
+    // scratch
+    Buf plan, act_start, act_cnt, chunks, item_off, partial;
+    Buf sel_min, sel_cnt;
+    Buf step_idx, step_na, step_T, step_out, phi, counters;
+    std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+void drop_graphs(hermite_ctx* c)
+{
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+// Grow a scratch buffer; every growth invalidates captured graphs.
+int ensure(hermite_ctx* c, Buf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return HERMITE_OK;
+    drop_graphs(c);
+    if (b.p) {
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(HERMITE_ENOMEM, "scratch allocation of %zu bytes failed", bytes);
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return HERMITE_OK;
+}
+
+int check_ctx(hermite_ctx* c)
+{
+    if (!c) return fail(HERMITE_EINVAL, "null context");
+    HIP_OK(hipSetDevice(c->device));
+    return HERMITE_OK;
+}
+
+int check_state(const hermite_state* s)
+{
+    if (!s) return fail(HERMITE_EINVAL, "null state");
+    if (s->n < 1 || s->n > INT32_MAX)
+        return fail(HERMITE_EINVAL, "n = %lld out of range [1, 2^31-1]", (long long)s->n);
+    if (s->tick_bits < 1 || s->tick_bits > 52)
+        return fail(HERMITE_EINVAL, "tick_bits = %d out of range [1, 52]", s->tick_bits);
+    if (!s->m || !s->x || !s->v || !s->a || !s->j || !s->xp || !s->vp || !s->pot || !s->t || !s->dt)
+        return fail(HERMITE_EINVAL, "null pointer in hermite_state");
+    return HERMITE_OK;
+}
+
+int check_precision(int precision)
+{
+    if (precision < HERMITE_FP64 || precision > HERMITE_MIXED_2F)
+        return fail(HERMITE_EINVAL, "unknown precision %d", precision);
+    return HERMITE_OK;
+}
+
+int check_eps2(double eps2)
+{
+    if (!(eps2 >= 0.0) || std::isinf(eps2))
+        return fail(HERMITE_EINVAL, "eps2 must be finite and >= 0");
+    return HERMITE_OK;
+}
+
+int check_clusters(const hermite_clusters* cl, int64_t n)
+{
+    if (!cl) return HERMITE_OK;
+    if (cl->n_clusters < 1) return fail(HERMITE_EINVAL, "n_clusters must be >= 1");
+    if (!cl->offsets || !cl->eps2) return fail(HERMITE_EINVAL, "null cluster arrays");
+    if (cl->max_size < 1 || cl->max_size > n)
+        return fail(HERMITE_EINVAL, "cluster max_size %lld out of range [1, n]",
+                    (long long)cl->max_size);
+    return HERMITE_OK;
+}
+
+int check_dt(const hermite_dt_params* p, int tick_bits)
+{
+    if (!p) return fail(HERMITE_EINVAL, "null dt params");
+    if (!(p->eta > 0.0) || std::isinf(p->eta)) return fail(HERMITE_EINVAL, "eta must be > 0");
+    if (p->form != HERMITE_DT_PAPER && p->form != HERMITE_DT_AARSETH)
+        return fail(HERMITE_EINVAL, "unknown timestep form %d", p->form);
+    if (p->k_min < 0 || p->k_max < p->k_min || p->k_max > tick_bits)
+        return fail(HERMITE_EINVAL, "need 0 <= k_min <= k_max <= tick_bits (%d, %d, %d)",
+                    p->k_min, p->k_max, tick_bits);
+    return HERMITE_OK;
+}
+
+// Default launch shape: two active particles per lane (variant 1), five
+// persistent workgroups per CU, and a j-split that gives every resident
+// lane work (twice over for FP64, whose longer dependency chains gain from
+// more, smaller items).  Chosen from a sweep of these parameters at
+// N = 65536 on gfx950; hermite_autotune refines it per size.
+hermite_tuning default_tuning(const hermite_ctx* c, int precision)
+{
+    hermite_tuning t;
+    t.variant = 1;
+    t.wg_per_cu = 5;
+    t.target_lanes = c->n_cu * t.wg_per_cu * kWG * (precision == HERMITE_FP64 ? 2 : 1);
+    t.min_j_per_lane = 64;
+    return t;
+}
+
+// Fills the sweep arguments and makes sure the scratch they point to exists.
+int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                  const double* xp, const double* vp, const int32_t* idx,
+                  const int32_t* n_act_dev, int32_t n_act_max, double eps2,
+                  const hermite_tuning& tu, double* acc, double* jerk, double* pot,
+                  SweepArgs* a)
+{
+    const int C = cl ? cl->n_clusters : 1;
+    CHECK(ensure(c, c->plan, sizeof(SweepPlan)));
+    CHECK(ensure(c, c->act_start, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->act_cnt, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->chunks, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->item_off, sizeof(int32_t) * (C + 1)));
+    const int64_t cap = (int64_t)7 * 16 * std::max<int64_t>(n_act_max, 1024);
+    CHECK(ensure(c, c->partial, sizeof(double) * cap));
+    CHECK(ensure(c, c->counters, sizeof(int64_t) * 8));
+    std::memset(a, 0, sizeof *a);
+    a->xp = xp;
+    a->vp = vp;
+    a->m = s->m;
+    a->n = s->n;
+    a->idx = idx;
+    a->n_act_dev = n_act_dev;
+    a->n_act_max = n_act_max;
+    a->n_clusters = C;
+    a->offsets = cl ? cl->offsets : nullptr;
+    a->eps2_c = cl ? cl->eps2 : nullptr;
+    a->eps2 = eps2;
+    a->n_cmax = cl ? cl->max_size : s->n;
+    a->plan = (SweepPlan*)c->plan.p;
+    a->act_start = (int32_t*)c->act_start.p;
+    a->act_cnt = (int32_t*)c->act_cnt.p;
+    a->chunks = (int32_t*)c->chunks.p;
+    a->item_off = (int32_t*)c->item_off.p;
+    a->partial = (double*)c->partial.p;
+    a->partial_cap = (int64_t)(c->partial.bytes / sizeof(double));
+    a->target_lanes = tu.target_lanes;
+    a->min_j_per_lane = tu.min_j_per_lane;
+    a->counters = (int64_t*)c->counters.p;
+    a->acc = acc;
+    a->jerk = jerk;
+    a->pot = pot;
+    return HERMITE_OK;
+}
+
+int run_force(hermite_ctx* c, const SweepArgs& a, int precision, const hermite_tuning& tu,
+              bool pot_only, hipStream_t st)
+{
+    const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
+    HIP_OK(launch_force(a, precision, tu.variant, grid, pot_only, st));
+    return HERMITE_OK;
+}
+
+int ensure_step_scratch(hermite_ctx* c, int64_t n)
+{
+    CHECK(ensure(c, c->step_idx, sizeof(int32_t) * n));
+    CHECK(ensure(c, c->step_na, sizeof(int32_t) * 2));
+    CHECK(ensure(c, c->step_T, sizeof(int64_t) * 2));
+    CHECK(ensure(c, c->step_out, sizeof(double) * 7 * n));
+    const int nb = select_blocks(n);
+    CHECK(ensure(c, c->sel_min, sizeof(int64_t) * nb));
+    CHECK(ensure(c, c->sel_cnt, sizeof(int32_t) * nb));
+    CHECK(ensure(c, c->counters, sizeof(int64_t) * 8));
+    return HERMITE_OK;
+}
+
+// One block step on stream st using the context's step scratch.
+int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                 double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
+                 hipStream_t st)
+{
+    const int64_t n = s->n;
+    int32_t* idx = (int32_t*)c->step_idx.p;
+    int32_t* na = (int32_t*)c->step_na.p;
+    int64_t* T = (int64_t*)c->step_T.p;
+    double* out = (double*)c->step_out.p;
+    int64_t* counters = (int64_t*)c->counters.p;
+    HIP_OK(launch_select(n, s->t, s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
+                         (int32_t*)c->sel_cnt.p, counters, st));
+    HIP_OK(launch_predict(n, s->tick_bits, s->x, s->v, s->a, s->j, s->t, T, 0, na,
+                          s->xp, s->vp, st));
+    SweepArgs a;
+    const hermite_tuning& tu = c->tuning[precision];
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, na, (int32_t)n, eps2, tu, out,
+                        out + 3 * n, out + 6 * n, &a));
+    CHECK(run_force(c, a, precision, tu, false, st));
+    CorrectArgs ca;
+    std::memset(&ca, 0, sizeof ca);
+    ca.n = n;
+    ca.tick_bits = s->tick_bits;
+    ca.idx = idx;
+    ca.n_act_dev = na;
+    ca.n_act_max = (int32_t)n;
+    ca.T_dev = T;
+    ca.xp = s->xp;
+    ca.vp = s->vp;
+    ca.acc1 = out;
+    ca.jrk1 = out + 3 * n;
+    ca.pot1 = out + 6 * n;
+    ca.x = s->x;
+    ca.v = s->v;
+    ca.a = s->a;
+    ca.j = s->j;
+    ca.pot = s->pot;
+    ca.t = s->t;
+    ca.dt = s->dt;
+    ca.eta = p->eta;
+    ca.form = p->form;
+    ca.k_min = p->k_min;
+    ca.k_max = p->k_max;
+    ca.counters = counters;
+    HIP_OK(launch_correct(ca, st));
+    return HERMITE_OK;
+}
+
+std::string step_key(const hermite_state* s, const hermite_clusters* cl, double eps2,
+                     int precision, const hermite_dt_params* p, int64_t T_end,
+                     const hermite_tuning& tu)
+{
+    std::ostringstream k;
+    k << s->n << '|' << s->tick_bits << '|' << (const void*)s->m << (void*)s->x
+      << (void*)s->v << (void*)s->a << (void*)s->j << (void*)s->xp << (void*)s->vp
+      << (void*)s->pot << (void*)s->t << (void*)s->dt << '|';
+    if (cl)
+        k << cl->n_clusters << ',' << cl->max_size << ',' << (const void*)cl->offsets
+          << (const void*)cl->eps2;
+    uint64_t eb;
+    std::memcpy(&eb, &eps2, 8);
+    uint64_t etab;
+    std::memcpy(&etab, &p->eta, 8);
+    k << '|' << eb << '|' << precision << '|' << etab << ',' << p->form << ','
+      << p->k_min << ',' << p->k_max << '|' << T_end << '|' << tu.target_lanes << ','
+      << tu.wg_per_cu << ',' << tu.min_j_per_lane << ',' << tu.variant;
+    return k.str();
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* hermite_last_error(void) { return g_err.c_str(); }
+
+int hermite_create(int device, hermite_ctx** out)
+{
+    if (!out) return fail(HERMITE_EINVAL, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        return fail(HERMITE_ENODEV, "no HIP device available");
+    }
+    if (device < 0 || device >= count)
+        return fail(HERMITE_ENODEV, "device %d not in [0, %d)", device, count);
+    HIP_OK(hipSetDevice(device));
+    hermite_ctx* c = new hermite_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return fail(HERMITE_EHIP, "hipGetDeviceProperties failed");
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(HERMITE_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    for (int p = 0; p < 3; ++p) c->tuning[p] = default_tuning(c, p);
+    int rc = ensure(c, c->counters, sizeof(int64_t) * 8);
+    if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * 8) != hipSuccess)
+        rc = fail(HERMITE_EHIP, "hipMemset of counters failed");
+    if (rc != HERMITE_OK) {
+        hermite_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return HERMITE_OK;
+}
+
+int hermite_destroy(hermite_ctx* c)
+{
+    if (!c) return HERMITE_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(c);
+    Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
+                   &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
+                   &c->step_T, &c->step_out, &c->phi, &c->counters};
+    for (Buf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return HERMITE_OK;
+}
+
+int hermite_sync(hermite_ctx* c, void* stream)
+{
+    CHECK(check_ctx(c));
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    HIP_OK(hipGetLastError());
+    return HERMITE_OK;
+}
+
+int hermite_select_block(hermite_ctx* c, const hermite_state* s, int32_t* idx_out,
+                         int32_t* n_act_dev, int64_t* T_dev, int64_t T_end, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    if (!idx_out || !n_act_dev || !T_dev) return fail(HERMITE_EINVAL, "null output pointer");
+    const int nb = select_blocks(s->n);
+    CHECK(ensure(c, c->sel_min, sizeof(int64_t) * nb));
+    CHECK(ensure(c, c->sel_cnt, sizeof(int32_t) * nb));
+    HIP_OK(launch_select(s->n, s->t, s->dt, T_end, idx_out, n_act_dev, T_dev,
+                         (int64_t*)c->sel_min.p, (int32_t*)c->sel_cnt.p,
+                         (int64_t*)c->counters.p, (hipStream_t)stream));
+    return HERMITE_OK;
+}
+
+int hermite_predict(hermite_ctx* c, const hermite_state* s, const int64_t* T_dev,
+                    int64_t T_host, const int32_t* n_act_dev, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    HIP_OK(launch_predict(s->n, s->tick_bits, s->x, s->v, s->a, s->j, s->t, T_dev, T_host,
+                          n_act_dev, s->xp, s->vp, (hipStream_t)stream));
+    return HERMITE_OK;
+}
+
+int hermite_force_jerk(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                       const int32_t* idx, const int32_t* n_act_dev, int32_t n_act_max,
+                       double eps2, int precision, double* acc, double* jerk, double* pot,
+                       void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    if (n_act_max < 0 || n_act_max > s->n)
+        return fail(HERMITE_EINVAL, "n_act_max = %d out of range [0, n]", n_act_max);
+    if (n_act_max == 0) return HERMITE_OK;
+    if (!idx && n_act_max != s->n)
+        return fail(HERMITE_EINVAL, "identity index list needs n_act_max == n");
+    if (!acc || !jerk) return fail(HERMITE_EINVAL, "null output pointer");
+    SweepArgs a;
+    const hermite_tuning& tu = c->tuning[precision];
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, tu, acc,
+                        jerk, pot, &a));
+    return run_force(c, a, precision, tu, false, (hipStream_t)stream);
+}
+
+int hermite_correct(hermite_ctx* c, const hermite_state* s, const int32_t* idx,
+                    const int32_t* n_act_dev, int32_t n_act_max, const int64_t* T_dev,
+                    int64_t T_host, const double* acc, const double* jerk,
+                    const double* pot, const hermite_dt_params* p, double* crit_out,
+                    void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_dt(p, s->tick_bits));
+    if (n_act_max < 0 || n_act_max > s->n)
+        return fail(HERMITE_EINVAL, "n_act_max = %d out of range [0, n]", n_act_max);
+    if (n_act_max == 0) return HERMITE_OK;
+    if (!idx && n_act_max != s->n)
+        return fail(HERMITE_EINVAL, "identity index list needs n_act_max == n");
+    if (!acc || !jerk) return fail(HERMITE_EINVAL, "null input pointer");
+    CorrectArgs ca;
+    std::memset(&ca, 0, sizeof ca);
+    ca.n = s->n;
+    ca.tick_bits = s->tick_bits;
+    ca.idx = idx;
+    ca.n_act_dev = n_act_dev;
+    ca.n_act_max = n_act_max;
+    ca.T_dev = T_dev;
+    ca.T_host = T_host;
+    ca.xp = s->xp;
+    ca.vp = s->vp;
+    ca.acc1 = acc;
+    ca.jrk1 = jerk;
+    ca.pot1 = pot;
+    ca.x = s->x;
+    ca.v = s->v;
+    ca.a = s->a;
+    ca.j = s->j;
+    ca.pot = s->pot;
+    ca.t = s->t;
+    ca.dt = s->dt;
+    ca.eta = p->eta;
+    ca.form = p->form;
+    ca.k_min = p->k_min;
+    ca.k_max = p->k_max;
+    ca.crit_out = crit_out;
+    ca.counters = (int64_t*)c->counters.p;
+    HIP_OK(launch_correct(ca, (hipStream_t)stream));
+    return HERMITE_OK;
+}
+
+int hermite_init_dt(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* p,
+                    void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_dt(p, s->tick_bits));
+    HIP_OK(launch_init_dt(s->n, s->tick_bits, s->a, s->j, s->t, s->dt, p->eta, p->form,
+                          p->k_min, p->k_max, (int64_t*)c->counters.p, (hipStream_t)stream));
+    return HERMITE_OK;
+}
+
+int hermite_initialize(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                       double eps2, int precision, const hermite_dt_params* p, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    CHECK(check_dt(p, s->tick_bits));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OK(launch_copy2(3 * s->n, s->x, s->xp, s->v, s->vp, st));
+    SweepArgs a;
+    const hermite_tuning& tu = c->tuning[precision];
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, nullptr, nullptr, (int32_t)s->n, eps2, tu,
+                        s->a, s->j, s->pot, &a));
+    CHECK(run_force(c, a, precision, tu, false, st));
+    HIP_OK(launch_init_dt(s->n, s->tick_bits, s->a, s->j, s->t, s->dt, p->eta, p->form,
+                          p->k_min, p->k_max, (int64_t*)c->counters.p, st));
+    return HERMITE_OK;
+}
+
+int hermite_energy(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                   double eps2, double* out_dev, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    if (!out_dev) return fail(HERMITE_EINVAL, "null output pointer");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(ensure(c, c->phi, sizeof(double) * s->n));
+    double* phi = (double*)c->phi.p;
+    SweepArgs a;
+    const hermite_tuning& tu = c->tuning[HERMITE_FP64];
+    CHECK(prepare_sweep(c, s, cl, s->x, s->v, nullptr, nullptr, (int32_t)s->n, eps2, tu,
+                        phi, nullptr, phi, &a));
+    a.counters = nullptr;
+    CHECK(run_force(c, a, HERMITE_FP64, tu, true, st));
+    HIP_OK(launch_energy_reduce(s->n, cl ? cl->n_clusters : 1, cl ? cl->offsets : nullptr,
+                                s->m, s->v, phi, out_dev, st));
+    return HERMITE_OK;
+}
+
+int hermite_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                 double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
+                 int use_graph, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    CHECK(check_dt(p, s->tick_bits));
+    CHECK(ensure_step_scratch(c, s->n));
+    // make sure the sweep scratch exists before any capture
+    {
+        SweepArgs a;
+        double* out = (double*)c->step_out.p;
+        CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, (int32_t*)c->step_idx.p,
+                            (int32_t*)c->step_na.p, (int32_t)s->n, eps2,
+                            c->tuning[precision], out, out + 3 * s->n, out + 6 * s->n, &a));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (!use_graph) return enqueue_step(c, s, cl, eps2, precision, p, T_end, st);
+
+    const std::string key = step_key(s, cl, eps2, precision, p, T_end, c->tuning[precision]);
+    GraphEntry* g = nullptr;
+    for (auto& e : c->graphs)
+        if (e.key == key) g = &e;
+    if (!g) {
+        if (c->graphs.size() >= 8) {
+            auto& e = c->graphs.front();
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            if (e.graph) (void)hipGraphDestroy(e.graph);
+            c->graphs.erase(c->graphs.begin());
+        }
+        GraphEntry e;
+        e.key = key;
+        HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(c, s, cl, eps2, precision, p, T_end, c->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+        if (rc != HERMITE_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess)
+            return fail(HERMITE_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        e.graph = graph;
+        hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(HERMITE_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        c->graphs.push_back(e);
+        g = &c->graphs.back();
+    }
+    HIP_OK(hipGraphLaunch(g->exec, st));
+    return HERMITE_OK;
+}
+
+int hermite_counters(hermite_ctx* c, int64_t out[5], void* stream)
+{
+    CHECK(check_ctx(c));
+    if (!out) return fail(HERMITE_EINVAL, "null output pointer");
+    int64_t h[8];
+    HIP_OK(hipMemcpyAsync(h, c->counters.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    for (int k = 0; k < 5; ++k) out[k] = h[k];
+    return HERMITE_OK;
+}
+
+int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
+                int use_graph, int32_t sync_every, int64_t* steps_out,
+                int64_t* interactions_out, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_dt(p, s->tick_bits));
+    if (sync_every < 1) return fail(HERMITE_EINVAL, "sync_every must be >= 1");
+    const int64_t dtmax = ((int64_t)1) << (s->tick_bits - p->k_min);
+    if (T_end < 0 || T_end % dtmax != 0)
+        return fail(HERMITE_EINVAL, "T_end must be a non-negative multiple of 2^(tick_bits-k_min)");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t c0[5], c1[5];
+    CHECK(hermite_counters(c, c0, stream));
+    for (;;) {
+        for (int k = 0; k < sync_every; ++k)
+            CHECK(hermite_step(c, s, cl, eps2, precision, p, T_end, use_graph, stream));
+        int64_t T = 0;
+        int32_t na = 0;
+        HIP_OK(hipMemcpyAsync(&T, c->step_T.p, sizeof T, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(&na, c->step_na.p, sizeof na, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (na == 0 || T >= T_end) break;
+    }
+    CHECK(hermite_counters(c, c1, stream));
+    if (steps_out) *steps_out = c1[0] - c0[0];
+    if (interactions_out) *interactions_out = c1[1] - c0[1];
+    return HERMITE_OK;
+}
+
+int hermite_get_tuning(hermite_ctx* c, int precision, hermite_tuning* out)
+{
+    if (!c || !out) return fail(HERMITE_EINVAL, "null argument");
+    CHECK(check_precision(precision));
+    *out = c->tuning[precision];
+    return HERMITE_OK;
+}
+
+int hermite_set_tuning(hermite_ctx* c, int precision, const hermite_tuning* in)
+{
+    if (!c || !in) return fail(HERMITE_EINVAL, "null argument");
+    CHECK(check_precision(precision));
+    if (in->wg_per_cu < 1 || in->wg_per_cu > 64 || in->target_lanes < kWG ||
+        in->min_j_per_lane < 1 || in->variant < 0 || in->variant > 1)
+        return fail(HERMITE_EINVAL, "tuning out of range");
+    c->tuning[precision] = *in;
+    return HERMITE_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate launch shapes with HIP events and keeps the
+// fastest one whose output agrees with the default shape.
+// ---------------------------------------------------------------------------
+namespace {
+
+int64_t pow2_bucket(int64_t v)
+{
+    int64_t b = 1;
+    while (b < v) b <<= 1;
+    return b;
+}
+
+std::string cache_key(const hermite_ctx* c, int precision, int64_t n, int32_t n_act)
+{
+    std::ostringstream k;
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    std::string arch = c->arch.substr(0, c->arch.find(':'));
+    k << arch << "|hip" << rt << "|p" << precision << "|n" << pow2_bucket(n) << "|a"
+      << pow2_bucket(n_act);
+    return k.str();
+}
+
+// The cache is a JSON object with one entry per line:
+//   "key": {"target_lanes": T, "wg_per_cu": W, "min_j_per_lane": M, "variant": V, "us": U},
+std::map<std::string, std::string> read_cache(const char* path)
+{
+    std::map<std::string, std::string> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"');
+        if (q0 == std::string::npos) continue;
+        const size_t q1 = line.find('"', q0 + 1);
+        const size_t b0 = line.find('{', q1 == std::string::npos ? 0 : q1);
+        const size_t b1 = line.rfind('}');
+        if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos || b1 < b0)
+            continue;
+        m[line.substr(q0 + 1, q1 - q0 - 1)] = line.substr(b0, b1 - b0 + 1);
+    }
+    return m;
+}
+
+bool field(const std::string& obj, const char* name, double* out)
+{
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t p = obj.find(pat);
+    if (p == std::string::npos) return false;
+    *out = std::strtod(obj.c_str() + p + pat.size(), nullptr);
+    return true;
+}
+
+int write_cache(const char* path, const std::map<std::string, std::string>& m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return fail(HERMITE_EINVAL, "cannot write tuning cache %s", path);
+        f << "{\n";
+        size_t k = 0;
+        for (const auto& e : m) {
+            f << " \"" << e.first << "\": " << e.second << (++k < m.size() ? ",\n" : "\n");
+        }
+        f << "}\n";
+    }
+    if (std::rename(tmp.c_str(), path) != 0)
+        return fail(HERMITE_EINVAL, "cannot replace tuning cache %s", path);
+    return HERMITE_OK;
+}
+
+double max_rel_diff(const std::vector<double>& a, const std::vector<double>& b, int64_t na,
+                    int q0, int q1)
+{
+    // max over particles of |a - b| / |b| for the vector (or scalar) rows
+    // q0..q1-1; particles with a zero reference norm compare absolutely.
+    double worst = 0.0;
+    for (int64_t p = 0; p < na; ++p) {
+        double dn = 0.0, rn = 0.0;
+        for (int q = q0; q < q1; ++q) {
+            const double d = a[q * na + p] - b[q * na + p];
+            dn += d * d;
+            rn += b[q * na + p] * b[q * na + p];
+        }
+        const double r = rn > 0.0 ? std::sqrt(dn / rn) : std::sqrt(dn);
+        if (!(r <= worst)) worst = r;
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hermite_autotune(hermite_ctx* c, const hermite_state* s, double eps2, int precision,
+                     int32_t n_act, const char* cache_path, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_eps2(eps2));
+    if (n_act < 1 || n_act > s->n) return fail(HERMITE_EINVAL, "n_act out of range [1, n]");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(ensure(c, c->step_idx, sizeof(int32_t) * s->n));
+    int32_t* idx = (int32_t*)c->step_idx.p;
+    HIP_OK(launch_iota(n_act, idx, st));
+    double* out = nullptr;
+    HIP_OK(hipMalloc(&out, sizeof(double) * 7 * (size_t)n_act));
+    std::vector<double> ref(7 * (size_t)n_act), got(7 * (size_t)n_act);
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const hermite_tuning base = default_tuning(c, precision);
+    auto run_p = [&](int prec, const hermite_tuning& tu, int reps, double* us,
+                     std::vector<double>* res) -> int {
+        SweepArgs a;
+        CHECK(prepare_sweep(c, s, nullptr, s->xp, s->vp, idx, nullptr, n_act, eps2, tu, out,
+                            out + 3 * (size_t)n_act, out + 6 * (size_t)n_act, &a));
+        a.counters = nullptr;
+        CHECK(run_force(c, a, prec, tu, false, st));   // warm-up
+        HIP_OK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) CHECK(run_force(c, a, prec, tu, false, st));
+        HIP_OK(hipEventRecord(e1, st));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        *us = 1000.0 * ms / reps;
+        if (res)
+            HIP_OK(hipMemcpy(res->data(), out, sizeof(double) * res->size(),
+                             hipMemcpyDeviceToHost));
+        return HERMITE_OK;
+    };
+    auto run = [&](const hermite_tuning& tu, int reps, double* us,
+                   std::vector<double>* res) -> int {
+        return run_p(precision, tu, reps, us, res);
+    };
+    // Accuracy guard: every candidate is compared with an FP64 sweep of the
+    // same particles; it must be as close to it as the tolerance of its
+    // precision, or (mixed) as close as the default shape is.
+    auto errs = [&](const std::vector<double>& g, const std::vector<double>& r, double e[3]) {
+        e[0] = max_rel_diff(g, r, n_act, 0, 3);
+        e[1] = max_rel_diff(g, r, n_act, 3, 6);
+        e[2] = max_rel_diff(g, r, n_act, 6, 7);
+    };
+    int rc = HERMITE_OK;
+    double best_us = 0.0;
+    hermite_tuning best = base;
+    const double tol = precision == HERMITE_FP64 ? 1e-13 : 1e-6;
+    double limit[3] = {tol, tol, tol};
+    std::vector<double> ref64(7 * (size_t)n_act);
+    do {
+        double us;
+        rc = run_p(HERMITE_FP64, default_tuning(c, HERMITE_FP64), 1, &us, &ref64);
+        if (rc != HERMITE_OK) break;
+        rc = run(base, 3, &us, &ref);
+        if (rc != HERMITE_OK) break;
+        best_us = us;
+        double e[3];
+        errs(ref, ref64, e);
+        for (int q = 0; q < 3; ++q) limit[q] = std::max(tol, 1.5 * e[q]);
+        const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{64}
+                                                   : std::vector<int>{16, 32, 64, 128};
+        for (int var = 0; var <= 1 && rc == HERMITE_OK; ++var) {
+            for (int w = 2; w <= 8 && rc == HERMITE_OK; ++w) {
+                for (int f : {1, 2, 4}) {
+                    for (int mj : mjs) {
+                        hermite_tuning tu;
+                        tu.wg_per_cu = w;
+                        tu.target_lanes = c->n_cu * w * kWG * f;
+                        tu.min_j_per_lane = mj;
+                        tu.variant = var;
+                        rc = run(tu, 3, &us, &got);
+                        if (rc != HERMITE_OK) break;
+                        double ge[3];
+                        errs(got, ref64, ge);
+                        const bool ok = ge[0] <= limit[0] && ge[1] <= limit[1] &&
+                                        ge[2] <= limit[2];
+                        if (ok && us < best_us) {
+                            best_us = us;
+                            best = tu;
+                        }
+                    }
+                    if (rc != HERMITE_OK) break;
+                }
+            }
+        }
+    } while (0);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    CHECK(rc);
+    c->tuning[precision] = best;
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        std::ostringstream o;
+        o << "{\"target_lanes\": " << best.target_lanes << ", \"wg_per_cu\": " << best.wg_per_cu
+          << ", \"min_j_per_lane\": " << best.min_j_per_lane << ", \"variant\": "
+          << best.variant << ", \"us\": " << best_us << "}";
+        m[cache_key(c, precision, s->n, n_act)] = o.str();
+        CHECK(write_cache(cache_path, m));
+    }
+    return HERMITE_OK;
+}
+
+int hermite_load_tuning(hermite_ctx* c, const char* cache_path, int precision, int64_t n,
+                        int32_t n_act)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_precision(precision));
+    if (!cache_path) return fail(HERMITE_EINVAL, "null cache path");
+    const auto m = read_cache(cache_path);
+    const auto it = m.find(cache_key(c, precision, n, n_act));
+    if (it == m.end()) return fail(HERMITE_EINVAL, "no tuning entry for this device and size");
+    double tl, wg, mj, var;
+    if (!field(it->second, "target_lanes", &tl) || !field(it->second, "wg_per_cu", &wg) ||
+        !field(it->second, "min_j_per_lane", &mj) || !field(it->second, "variant", &var))
+        return fail(HERMITE_EINVAL, "malformed tuning entry");
+    hermite_tuning t;
+    t.target_lanes = (int32_t)tl;
+    t.wg_per_cu = (int32_t)wg;
+    t.min_j_per_lane = (int32_t)mj;
+    t.variant = (int32_t)var;
+    return hermite_set_tuning(c, precision, &t);
+}
+
+}  // extern "C"

@@ -1,0 +1,400 @@
+// O(N) and O(N_act) stages of a block step on gfx950: block selection,
+// predictor, corrector + next timestep, first timestep, energy sums.
+// All are memory/latency bound; every thread handles whole particles and
+// reads/writes SoA arrays with unit stride.
+#include "hermite_internal.h"
+
+namespace hm {
+namespace {
+
+constexpr int kSelPer = 4;                 // particles per thread in select
+constexpr int kSelBlock = kWG * kSelPer;   // particles per select block
+
+// ---- block selection (procedure step 1) ---------------------------------
+// Stage 1: per-block minimum of t_i + dt_i.
+__global__ void __launch_bounds__(kWG) sel_min_kernel(int64_t n, const int64_t* t,
+                                                      const int64_t* dt,
+                                                      int64_t* block_min)
+{
+    __shared__ int64_t sh[kWG];
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock;
+    int64_t v = INT64_MAX;
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
+        if (i < n) {
+            const int64_t e = t[i] + dt[i];
+            v = e < v ? e : v;
+        }
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const int64_t o = sh[threadIdx.x + s];
+            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_min[blockIdx.x] = sh[0];
+}
+
+__device__ int64_t block_min_all(const int64_t* block_min, int nb, int64_t* sh)
+{
+    int64_t v = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kWG) v = block_min[b] < v ? block_min[b] : v;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const int64_t o = sh[threadIdx.x + s];
+            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    const int64_t T = sh[0];
+    __syncthreads();
+    return T;
+}
+
+// Stage 2: T from all block minima; count the active particles per block.
+__global__ void __launch_bounds__(kWG) sel_count_kernel(int64_t n, const int64_t* t,
+                                                        const int64_t* dt,
+                                                        const int64_t* block_min,
+                                                        int nb, int32_t* block_cnt,
+                                                        int64_t* T_out)
+{
+    __shared__ int64_t sh[kWG];
+    __shared__ int32_t shc[kWG];
+    const int64_t T = block_min_all(block_min, nb, sh);
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock;
+    int32_t c = 0;
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
+        if (i < n && t[i] + dt[i] == T) ++c;
+    }
+    shc[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        block_cnt[blockIdx.x] = shc[0];
+        if (blockIdx.x == 0) *T_out = T;
+    }
+}
+
+// Stage 3: each block's output offset is the sum of the counts before it;
+// a block-wide scan places every active index in ascending order.
+__global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t* t,
+                                                        const int64_t* dt,
+                                                        const int32_t* block_cnt,
+                                                        int nb, const int64_t* T_in,
+                                                        int64_t T_end, int32_t* idx,
+                                                        int32_t* n_act,
+                                                        int64_t* counters)
+{
+    __shared__ int32_t sh[kWG];
+    const int64_t T = *T_in;
+    // offset of this block
+    int32_t pre = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kWG) pre += block_cnt[b];
+    sh[threadIdx.x] = pre;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const int32_t off = sh[0];
+    __syncthreads();
+    // this thread's particles are base + tid*kSelPer + r (contiguous per
+    // thread so that a scan over threads keeps ascending order)
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock + (int64_t)threadIdx.x * kSelPer;
+    bool f[kSelPer];
+    int32_t c = 0;
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + r;
+        f[r] = (i < n) && (t[i] + dt[i] == T);
+        c += f[r] ? 1 : 0;
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = 1; d < kWG; d <<= 1) {
+        const int32_t v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t pos = off + sh[threadIdx.x] - c;
+    const bool live = T <= T_end;
+    if (live) {
+        for (int r = 0; r < kSelPer; ++r)
+            if (f[r]) idx[pos++] = (int32_t)(base + r);
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == kWG - 1) {
+        const int32_t total = off + sh[kWG - 1];
+        const int32_t na = live ? total : 0;
+        *n_act = na;
+        if (counters) {
+            counters[0] += na > 0 ? 1 : 0;
+            counters[3] = T;
+            counters[4] = na;
+        }
+    }
+}
+
+// ---- predictor (equations (xpred), (vpred)) -----------------------------
+__global__ void __launch_bounds__(kWG) predict_kernel(int64_t n, double tick,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ a,
+                                                      const double* __restrict__ j,
+                                                      const int64_t* __restrict__ t,
+                                                      const int64_t* T_dev, int64_t T_host,
+                                                      const int32_t* n_act_dev,
+                                                      double* __restrict__ xp,
+                                                      double* __restrict__ vp)
+{
+    if (n_act_dev && *n_act_dev == 0) return;
+    const int64_t T = T_dev ? *T_dev : T_host;
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= n) return;
+    const double h = (double)(T - t[i]) * tick;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = d * n + i;
+        const double a2 = a[o] * 0.5;
+        const double j6 = j[o] * (1.0 / 6.0);
+        const double j2 = j[o] * 0.5;
+        xp[o] = fma(h, fma(h, fma(h, j6, a2), v[o]), x[o]);
+        vp[o] = fma(h, fma(h, j2, a[o]), v[o]);
+    }
+}
+
+// ---- timestep: Aarseth criterion and power-of-two quantisation ----------
+__device__ __forceinline__ double norm3(double a, double b, double c)
+{
+    return sqrt(fma(a, a, fma(b, b, c * c)));
+}
+
+__device__ int64_t quantize_dt(double crit, int k_old, int64_t T, int tick_bits,
+                               int k_min, int k_max, int* clamped)
+{
+    int k;
+    *clamped = 0;
+    if (__builtin_isnan(crit) || __builtin_isinf(crit)) {
+        k = k_min;
+    } else if (crit <= 0.0) {
+        k = k_max;
+        *clamped = 1;
+    } else {
+        int e;
+        frexp(crit, &e);            // crit in [2^(e-1), 2^e)
+        k = 1 - e;
+        if (k < k_min) k = k_min;
+        if (k > k_max) { k = k_max; *clamped = 1; }
+    }
+    if (k_old >= 0 && k < k_old - 1) k = k_old - 1;
+    while (k < k_max && (T & ((((int64_t)1) << (tick_bits - k)) - 1)) != 0) ++k;
+    return ((int64_t)1) << (tick_bits - k);
+}
+
+__device__ __forceinline__ int log2_ticks(int64_t dt)
+{
+    return 63 - __clzll((unsigned long long)dt);
+}
+
+// ---- corrector + next step (procedure steps 5-8) -------------------------
+__global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
+{
+    const int na = c.n_act_dev ? *c.n_act_dev : c.n_act_max;
+    const int p = blockIdx.x * kWG + threadIdx.x;
+    if (p >= na) return;
+    const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
+    const int64_t n = c.n;
+    const int64_t st = c.n_act_max;
+    const int i = c.idx ? c.idx[p] : p;
+    const double tick = ldexp(1.0, -c.tick_bits);
+    const int64_t dt_old = c.dt[i];
+    const double h = (double)dt_old * tick;
+    const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
+    double s1[3], cc[3], a1v[3], j1v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = d * n + i;
+        const double a0 = c.a[o], j0 = c.j[o];
+        const double a1 = c.acc1[d * st + p], j1 = c.jrk1[d * st + p];
+        const double da = a0 - a1;
+        const double s0 = 2.0 * (-3.0 * da - (2.0 * j0 + j1) * h) / h2;
+        const double c0 = 6.0 * (2.0 * da + (j0 + j1) * h) / h3;
+        c.x[o] = c.xp[o] + s0 * h4 / 24.0 + c0 * h5 / 120.0;
+        c.v[o] = c.vp[o] + s0 * h3 / 6.0 + c0 * h4 / 24.0;
+        c.a[o] = a1;
+        c.j[o] = j1;
+        s1[d] = fma(c0, h, s0);
+        cc[d] = c0;
+        a1v[d] = a1;
+        j1v[d] = j1;
+    }
+    if (c.pot1) c.pot[i] = c.pot1[p];
+    c.t[i] = T;
+    const double A = norm3(a1v[0], a1v[1], a1v[2]);
+    const double J = norm3(j1v[0], j1v[1], j1v[2]);
+    const double S = norm3(s1[0], s1[1], s1[2]);
+    const double Cn = norm3(cc[0], cc[1], cc[2]);
+    const double R = (A * S + J * J) / (J * Cn + S * S);
+    const double crit = c.form == 0 ? c.eta * sqrt(R) : sqrt(c.eta * R);
+    if (c.crit_out) c.crit_out[p] = crit;
+    const int k_old = c.tick_bits - log2_ticks(dt_old);
+    int cl;
+    c.dt[i] = quantize_dt(crit, k_old, T, c.tick_bits, c.k_min, c.k_max, &cl);
+    if (cl && c.counters) atomicAdd((unsigned long long*)&c.counters[2], 1ull);
+}
+
+__global__ void __launch_bounds__(kWG) init_dt_kernel(int64_t n, int tick_bits,
+                                                      const double* a, const double* j,
+                                                      int64_t* t, int64_t* dt,
+                                                      double eta_f, int k_min,
+                                                      int k_max, int64_t* counters)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= n) return;
+    const double A = norm3(a[i], a[n + i], a[2 * n + i]);
+    const double J = norm3(j[i], j[n + i], j[2 * n + i]);
+    const double crit = eta_f * A / J;
+    int cl;
+    t[i] = 0;
+    dt[i] = quantize_dt(crit, -1, 0, tick_bits, k_min, k_max, &cl);
+    if (cl && counters) atomicAdd((unsigned long long*)&counters[2], 1ull);
+}
+
+__global__ void __launch_bounds__(kWG) copy2_kernel(int64_t count, const double* s0,
+                                                    double* d0, const double* s1,
+                                                    double* d1)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= count) return;
+    d0[i] = s0[i];
+    d1[i] = s1[i];
+}
+
+// ---- energy: K = 1/2 sum m v^2, W = 1/2 sum m phi, per cluster -----------
+__global__ void __launch_bounds__(kWG) energy_reduce_kernel(int64_t n,
+                                                            const int64_t* offsets,
+                                                            const double* m,
+                                                            const double* v,
+                                                            const double* phi,
+                                                            double* out)
+{
+    __shared__ double sk[kWG], sw[kWG];
+    const int c = blockIdx.x;
+    const int64_t b = offsets ? offsets[c] : 0;
+    const int64_t e = offsets ? offsets[c + 1] : n;
+    double K = 0.0, W = 0.0;
+    for (int64_t i = b + threadIdx.x; i < e; i += kWG) {
+        const double v2 = fma(v[i], v[i], fma(v[n + i], v[n + i], v[2 * n + i] * v[2 * n + i]));
+        K = fma(0.5 * m[i], v2, K);
+        W = fma(0.5 * m[i], phi[i], W);
+    }
+    sk[threadIdx.x] = K;
+    sw[threadIdx.x] = W;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sk[threadIdx.x] += sk[threadIdx.x + s];
+            sw[threadIdx.x] += sw[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * c] = sk[0];
+        out[2 * c + 1] = sw[0];
+    }
+}
+
+__global__ void __launch_bounds__(kWG) iota_kernel(int32_t count, int32_t* out)
+{
+    const int i = blockIdx.x * kWG + threadIdx.x;
+    if (i < count) out[i] = i;
+}
+
+inline int nblocks(int64_t count, int per)
+{
+    return (int)((count + per - 1) / per);
+}
+
+}  // namespace
+
+int select_blocks(int64_t n) { return nblocks(n, kSelBlock); }
+
+hipError_t launch_select(int64_t n, const int64_t* t, const int64_t* dt,
+                         int64_t T_end, int32_t* idx, int32_t* n_act,
+                         int64_t* T, int64_t* block_min, int32_t* block_cnt,
+                         int64_t* counters, hipStream_t st)
+{
+    const int nb = nblocks(n, kSelBlock);
+    hipLaunchKernelGGL(sel_min_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min);
+    hipLaunchKernelGGL(sel_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                       (const int64_t*)block_min, nb, block_cnt, T);
+    hipLaunchKernelGGL(sel_write_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                       (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx,
+                       n_act, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(int64_t n, int tick_bits, const double* x,
+                          const double* v, const double* a, const double* j,
+                          const int64_t* t, const int64_t* T_dev,
+                          int64_t T_host, const int32_t* n_act_dev,
+                          double* xp, double* vp, hipStream_t st)
+{
+    const double tick = ldexp(1.0, -tick_bits);
+    hipLaunchKernelGGL(predict_kernel, dim3(nblocks(n, kWG)), dim3(kWG), 0, st, n,
+                       tick, x, v, a, j, t, T_dev, T_host, n_act_dev, xp, vp);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const CorrectArgs& c, hipStream_t st)
+{
+    hipLaunchKernelGGL(correct_kernel, dim3(nblocks(c.n_act_max, kWG)), dim3(kWG), 0,
+                       st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,
+                          const double* j, int64_t* t, int64_t* dt,
+                          double eta, int form, int k_min, int k_max,
+                          int64_t* counters, hipStream_t st)
+{
+    const double eta_f = form == 0 ? eta : sqrt(eta);
+    hipLaunchKernelGGL(init_dt_kernel, dim3(nblocks(n, kWG)), dim3(kWG), 0, st, n,
+                       tick_bits, a, j, t, dt, eta_f, k_min, k_max, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy2(int64_t count, const double* src0, double* dst0,
+                        const double* src1, double* dst1, hipStream_t st)
+{
+    hipLaunchKernelGGL(copy2_kernel, dim3(nblocks(count, kWG)), dim3(kWG), 0, st,
+                       count, src0, dst0, src1, dst1);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t count, int32_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(iota_kernel, dim3(nblocks(count, kWG)), dim3(kWG), 0, st, count,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(int64_t n, int n_clusters,
+                                const int64_t* offsets, const double* m,
+                                const double* v, const double* phi,
+                                double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(energy_reduce_kernel, dim3(n_clusters), dim3(kWG), 0, st, n,
+                       offsets, m, v, phi, out);
+    return hipGetLastError();
+}
+
+}  // namespace hm

@@ -1,0 +1,628 @@
+// The O(N_act * N) force / jerk / potential sweep on gfx950 (CDNA4).
+//
+// Equations (acc), (jrk), (pot) of Section 2: for every active i,
+//   a_i   = sum_{j != i} m_j r / s^{3/2}
+//   jrk_i = sum_{j != i} m_j / s^{3/2} (v - 3 (r.v) / s  r)
+//   phi_i = -sum_{j != i} m_j / s^{1/2}
+// with r = x_j - x_i, v = v_j - v_i, s = r^2 + eps^2.
+//
+// Design (GPU analogue of the paper's i-in-registers, j-streamed loop of
+// Section 3.3):
+//  * Work is a list of items (cluster, i-tile, j-chunk).  A persistent grid
+//    of workgroups pulls items from a device counter, so one launch serves
+//    any active count, ragged clusters and graph replays.
+//  * Each lane holds one active particle in registers.  When the active
+//    block is small, L lanes of a wave share one particle and take every
+//    L-th j; their sums are combined by a wave-shuffle butterfly.  Larger
+//    splits go across workgroups (j-chunks) and are added in a fixed order
+//    by the reduce kernel, so results are bitwise reproducible.
+//  * j-particles stream through LDS in tiles of kTJ, loaded with coalesced
+//    SoA reads; all lanes of a wave read the same LDS word when L = 1.
+//  * Self-interaction is removed by comparing indices (Section 3.3, the
+//    MASK block), but only in tiles that contain one of the wave's i.
+//  * Sums are blocked: a tile (FP64) or a run of K j (mixed) is summed
+//    into fresh accumulators before it is added to the running sum, which
+//    keeps rounding growth near sqrt(N/K) + sqrt(K) instead of sqrt(N).
+//
+// Precisions:
+//  FP64     all arithmetic binary64; 1/sqrt(s) from v_rsq_f64 refined by
+//           one third-order Newton step (Section 3.2's iteration taken one
+//           order further), ~1 ulp.
+//  MIXED    r and v subtracted in FP64 and rounded to FP32; s, 1/sqrt(s)
+//           (v_rsq_f32), and the pair terms in FP32; K-term FP32 partial
+//           sums added to FP64 running sums.
+//  MIXED_2F as MIXED, with the running sums held as two FP32 words
+//           (hi + lo) updated by Knuth's TwoSum.
+#include "hermite_internal.h"
+
+#include <type_traits>
+
+namespace hm {
+namespace {
+
+constexpr int kMixedK = 16;   // FP32 run length before an FP64 flush
+
+__device__ __forceinline__ double rsqrt_f64(double s)
+{
+    // y0 from the hardware; with e = 1 - s y0^2,
+    // 1/sqrt(s) = y0 (1 - e)^{-1/2} = y0 (1 + e/2 + 3 e^2 / 8 + ...).
+    const double y = __builtin_amdgcn_rsq(s);
+    const double h = s * y;
+    const double e = fma(-h, y, 1.0);
+    const double p = fma(e, 0.375, 0.5);
+    return fma(y * e, p, y);
+}
+
+template <typename T>
+__device__ __forceinline__ int upper_bound_i64(const int64_t* a, int count, T key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= (int64_t)key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int upper_bound_i32(const int32_t* a, int count, int key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int lower_bound_idx(const int32_t* a, int count, int64_t key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------
+// Plan: one workgroup turns the device-resident active count into a split
+// (lanes per particle L, chunk length jc) and a work list.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWG) plan_kernel(SweepArgs a)
+{
+    __shared__ int32_t s_items[kWG];
+    __shared__ int32_t s_cmax[kWG];
+    __shared__ int64_t s_inter[kWG];
+    __shared__ int32_t s_na, s_L, s_ti;
+    __shared__ int64_t s_jc;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int32_t na = a.n_act_dev ? *a.n_act_dev : a.n_act_max;
+        na = na < 0 ? 0 : (na > a.n_act_max ? a.n_act_max : na);
+        const int32_t nl = (na + a.ipl - 1) / a.ipl;   // lanes' worth of particles
+        int32_t L = 1;
+        while (L < 64 && (int64_t)nl * L * 2 <= (int64_t)a.target_lanes) L <<= 1;
+        const int64_t lanes = (int64_t)(nl > 0 ? nl : 1) * L;
+        int64_t S = (int64_t)a.target_lanes / lanes;
+        if (S < 1) S = 1;
+        int64_t jc = (a.n_cmax + S - 1) / S;
+        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
+        if (jc < jmin) jc = jmin;
+        jc = (jc + kTJ - 1) / kTJ * kTJ;
+        if (na > 0) {
+            const int64_t smax_cap = a.partial_cap / (7 * (int64_t)na);
+            const int64_t smax = (a.n_cmax + jc - 1) / jc;
+            if (smax > smax_cap) {
+                jc = (a.n_cmax + smax_cap - 1) / smax_cap;
+                jc = (jc + kTJ - 1) / kTJ * kTJ;
+            }
+        }
+        s_na = na; s_L = L; s_ti = a.ipl * (kWG / L); s_jc = jc;
+    }
+    __syncthreads();
+    const int32_t na = s_na, ti = s_ti;
+    const int64_t jc = s_jc;
+    const int C = a.n_clusters;
+    const int per = (C + kWG - 1) / kWG;
+    const int c0 = tid * per;
+    const int c1 = (c0 + per < C) ? c0 + per : C;
+    int32_t local = 0, cmax = 0;
+    int64_t inter = 0;
+    for (int c = c0; c < c1; ++c) {
+        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
+        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
+        int32_t st, cnt;
+        if (C == 1) {
+            st = 0; cnt = na;
+        } else if (a.idx == nullptr) {
+            const int64_t e = o1 < na ? o1 : na;
+            st = (int32_t)o0;
+            cnt = e > o0 ? (int32_t)(e - o0) : 0;
+        } else {
+            st = lower_bound_idx(a.idx, na, o0);
+            cnt = lower_bound_idx(a.idx, na, o1) - st;
+        }
+        const int32_t tiles = (cnt + ti - 1) / ti;
+        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
+        a.act_start[c] = st;
+        a.act_cnt[c] = cnt;
+        a.chunks[c] = ch;
+        local += tiles * ch;
+        cmax = ch > cmax ? ch : cmax;
+        inter += (int64_t)cnt * (o1 - o0);
+    }
+    s_items[tid] = local;
+    s_cmax[tid] = cmax;
+    s_inter[tid] = inter;
+    __syncthreads();
+    // inclusive scan of item counts (Hillis-Steele), max and sum
+    for (int d = 1; d < kWG; d <<= 1) {
+        int32_t v = tid >= d ? s_items[tid - d] : 0;
+        int32_t mx = tid >= d ? s_cmax[tid - d] : 0;
+        int64_t iv = tid >= d ? s_inter[tid - d] : 0;
+        __syncthreads();
+        s_items[tid] += v;
+        s_cmax[tid] = mx > s_cmax[tid] ? mx : s_cmax[tid];
+        s_inter[tid] += iv;
+        __syncthreads();
+    }
+    int32_t base = tid > 0 ? s_items[tid - 1] : 0;
+    for (int c = c0; c < c1; ++c) {
+        a.item_off[c] = base;
+        base += ((a.act_cnt[c] + ti - 1) / ti) * a.chunks[c];
+    }
+    if (tid == kWG - 1) {
+        a.item_off[C] = s_items[kWG - 1];
+        SweepPlan* P = a.plan;
+        P->n_act = na;
+        P->L = s_L;
+        P->ti = ti;
+        P->s_max = s_cmax[kWG - 1];
+        P->jc = jc;
+        P->total_items = s_items[kWG - 1];
+        P->next_item = 0u;
+        if (a.counters) {
+            a.counters[1] += s_inter[kWG - 1];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Accumulators and pair interactions
+// ------------------------------------------------------------------------
+struct I64 {   // i-particle in FP64
+    double x, y, z, vx, vy, vz;
+};
+
+struct SumD {  // FP64 sums: acc, jerk, sum of m/r
+    double ax, ay, az, jx, jy, jz, pp;
+    __device__ __forceinline__ void zero()
+    {
+        ax = ay = az = jx = jy = jz = pp = 0.0;
+    }
+    __device__ __forceinline__ void add(const SumD& o)
+    {
+        ax += o.ax; ay += o.ay; az += o.az;
+        jx += o.jx; jy += o.jy; jz += o.jz;
+        pp += o.pp;
+    }
+};
+
+struct SumF {  // FP32 run sums
+    float ax, ay, az, jx, jy, jz, pp;
+    __device__ __forceinline__ void zero()
+    {
+        ax = ay = az = jx = jy = jz = pp = 0.0f;
+    }
+};
+
+struct TwoF {  // one two-float running sum
+    float hi, lo;
+    __device__ __forceinline__ void add(float b)
+    {
+        const float s = hi + b;
+        const float bb = s - hi;
+        const float err = (hi - (s - bb)) + (b - bb);
+        hi = s;
+        lo += err;
+    }
+    __device__ __forceinline__ double value() const
+    {
+        return (double)hi + (double)lo;
+    }
+};
+
+struct Sum2F {
+    TwoF ax, ay, az, jx, jy, jz, pp;
+    __device__ __forceinline__ void zero()
+    {
+        ax = ay = az = jx = jy = jz = pp = TwoF{0.0f, 0.0f};
+    }
+};
+
+// One FP64 pair term: with b3 = 3 (r.v) / s,
+//   acc += m/s^{3/2} r,  jerk += m/s^{3/2} (v - b3 r),  pp += m/s^{1/2}.
+template <bool MASK>
+__device__ __forceinline__ void pair_f64(const I64& I, double eps2, double xj,
+                                         double yj, double zj, double vxj,
+                                         double vyj, double vzj, double mj,
+                                         bool self, SumD& S)
+{
+    const double dx = xj - I.x, dy = yj - I.y, dz = zj - I.z;
+    const double dvx = vxj - I.vx, dvy = vyj - I.vy, dvz = vzj - I.vz;
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+    double ri = rsqrt_f64(r2);
+    if (MASK) ri = self ? 0.0 : ri;
+    const double mr = mj * ri;
+    const double ri2 = ri * ri;
+    const double mr3 = mr * ri2;
+    const double rv = fma(dx, dvx, fma(dy, dvy, dz * dvz));
+    const double b3 = (rv * ri2) * 3.0;
+    S.pp += mr;
+    S.ax = fma(mr3, dx, S.ax);
+    S.ay = fma(mr3, dy, S.ay);
+    S.az = fma(mr3, dz, S.az);
+    S.jx = fma(mr3, fma(-b3, dx, dvx), S.jx);
+    S.jy = fma(mr3, fma(-b3, dy, dvy), S.jy);
+    S.jz = fma(mr3, fma(-b3, dz, dvz), S.jz);
+}
+
+template <bool MASK>
+__device__ __forceinline__ void pot_f64(const I64& I, double eps2, double xj,
+                                        double yj, double zj, double mj,
+                                        bool self, SumD& S)
+{
+    const double dx = xj - I.x, dy = yj - I.y, dz = zj - I.z;
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+    double ri = rsqrt_f64(r2);
+    if (MASK) ri = self ? 0.0 : ri;
+    S.pp = fma(mj, ri, S.pp);
+}
+
+// One mixed-precision pair term: FP64 differences, FP32 pair arithmetic.
+template <bool MASK>
+__device__ __forceinline__ void pair_mixed(const I64& I, float eps2f, double xj,
+                                           double yj, double zj, double vxj,
+                                           double vyj, double vzj, float mj,
+                                           bool self, SumF& S)
+{
+    const float dx = (float)(xj - I.x), dy = (float)(yj - I.y), dz = (float)(zj - I.z);
+    const float dvx = (float)(vxj - I.vx), dvy = (float)(vyj - I.vy),
+                dvz = (float)(vzj - I.vz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    if (MASK) ri = self ? 0.0f : ri;
+    const float mr = mj * ri;
+    const float ri2 = ri * ri;
+    const float mr3 = mr * ri2;
+    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+    const float b3 = (rv * ri2) * 3.0f;
+    S.pp += mr;
+    S.ax = fmaf(mr3, dx, S.ax);
+    S.ay = fmaf(mr3, dy, S.ay);
+    S.az = fmaf(mr3, dz, S.az);
+    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
+    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
+    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+}
+
+__device__ __forceinline__ void flush(SumF& f, SumD& d)
+{
+    d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
+    d.jx += (double)f.jx; d.jy += (double)f.jy; d.jz += (double)f.jz;
+    d.pp += (double)f.pp;
+    f.zero();
+}
+
+__device__ __forceinline__ void flush(SumF& f, Sum2F& d)
+{
+    d.ax.add(f.ax); d.ay.add(f.ay); d.az.add(f.az);
+    d.jx.add(f.jx); d.jy.add(f.jy); d.jz.add(f.jz);
+    d.pp.add(f.pp);
+    f.zero();
+}
+
+// LDS tile of j-particles (SoA).  Masses are FP32 in the mixed paths.
+template <typename MT>
+struct Tile {
+    double x[kTJ], y[kTJ], z[kTJ], vx[kTJ], vy[kTJ], vz[kTJ];
+    MT m[kTJ];
+};
+
+// ---- tile loops ---------------------------------------------------------
+// Each lane carries IPL active particles; every j read from LDS is used by
+// all of them (independent dependency chains, and IPL times fewer LDS
+// reads per interaction).
+template <bool MASK, int IPL>
+__device__ __forceinline__ void tile_f64(const Tile<double>& T, int cnt, int sub,
+                                         int L, int64_t tb, const int (&ii)[IPL],
+                                         const I64 (&I)[IPL], double eps2, SumD (&S)[IPL])
+{
+    constexpr int kUnroll = IPL == 1 ? 4 : 2;
+    SumD t[IPL];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) t[q].zero();
+#pragma unroll kUnroll
+    for (int jj = sub; jj < cnt; jj += L) {
+        const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+        const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj], mj = T.m[jj];
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const bool self = MASK && (tb + jj == (int64_t)ii[q]);
+            pair_f64<MASK>(I[q], eps2, xj, yj, zj, vxj, vyj, vzj, mj, self, t[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) S[q].add(t[q]);
+}
+
+template <bool MASK>
+__device__ __forceinline__ void tile_pot(const Tile<double>& T, int cnt, int sub,
+                                         int L, int64_t tb, int i, const I64& I,
+                                         double eps2, SumD& S)
+{
+    SumD t;
+    t.pp = 0.0;
+#pragma unroll 4
+    for (int jj = sub; jj < cnt; jj += L) {
+        const bool self = MASK && (tb + jj == (int64_t)i);
+        pot_f64<MASK>(I, eps2, T.x[jj], T.y[jj], T.z[jj], T.m[jj], self, t);
+    }
+    S.pp += t.pp;
+}
+
+template <bool MASK, int IPL, typename RUN>
+__device__ __forceinline__ void tile_mixed(const Tile<float>& T, int cnt, int sub,
+                                           int L, int64_t tb, const int (&ii)[IPL],
+                                           const I64 (&I)[IPL], float eps2f,
+                                           SumF (&f)[IPL], RUN (&S)[IPL])
+{
+    constexpr int kUnroll = IPL == 1 ? 4 : 2;
+    const int step = kMixedK * L;
+    for (int jb = 0; jb < cnt; jb += step) {
+        const int je = (jb + step < cnt) ? jb + step : cnt;
+#pragma unroll kUnroll
+        for (int jj = jb + sub; jj < je; jj += L) {
+            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+            const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
+            const float mj = T.m[jj];
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
+                pair_mixed<MASK>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, mj, self, f[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+    }
+}
+
+__device__ __forceinline__ double shfl_sum(double v, int L)
+{
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Final per-lane values: acc xyz, jerk xyz, pot (-sum m/r).
+__device__ __forceinline__ void finalize(const SumD& S, double out[7])
+{
+    out[0] = S.ax; out[1] = S.ay; out[2] = S.az;
+    out[3] = S.jx; out[4] = S.jy; out[5] = S.jz;
+    out[6] = -S.pp;
+}
+
+__device__ __forceinline__ void finalize(const Sum2F& S, double out[7])
+{
+    out[0] = S.ax.value(); out[1] = S.ay.value(); out[2] = S.az.value();
+    out[3] = S.jx.value(); out[4] = S.jy.value(); out[5] = S.jz.value();
+    out[6] = -S.pp.value();
+}
+
+// ------------------------------------------------------------------------
+// The persistent sweep kernel.
+//   PREC 0 = FP64, 1 = mixed (FP64 running sums), 2 = mixed two-float.
+//   POT_ONLY: potential only, FP64 (energy diagnostic).
+//   IPL: active particles per lane (1 or 2).  Lane `slot` of an item holds
+//   the item's particles slot, slot + kWG/L, ...
+// ------------------------------------------------------------------------
+template <int PREC, bool POT_ONLY, int IPL>
+__global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
+{
+    using MT = typename std::conditional<PREC == 0, double, float>::type;
+    using RUN = typename std::conditional<PREC == 2, Sum2F, SumD>::type;
+    __shared__ Tile<MT> T;
+    __shared__ int32_t s_item;
+
+    SweepPlan* P = a.plan;
+    const int na = P->n_act;
+    if (na == 0) return;
+    const int L = P->L;
+    const int ti = P->ti;
+    const int rows = kWG / L;          // lanes' slots per particle row
+    const int64_t jc = P->jc;
+    const int total = P->total_items;
+    const int tid = threadIdx.x;
+    const int slot = tid / L;
+    const int sub = tid & (L - 1);
+    const int C = a.n_clusters;
+    const int64_t n = a.n;
+
+    for (;;) {
+        if (tid == 0) s_item = (int32_t)atomicAdd(&P->next_item, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+
+        const int c = (C == 1) ? 0 : upper_bound_i32(a.item_off, C + 1, item) - 1;
+        const int local = item - a.item_off[c];
+        const int ch = a.chunks[c];
+        const int tile_i = local / ch;
+        const int k = local - tile_i * ch;
+        const int p0 = a.act_start[c] + tile_i * ti;
+        const int rem = a.act_cnt[c] - tile_i * ti;
+        const int pcnt = rem < ti ? rem : ti;
+        const int64_t cb = (C == 1) ? 0 : a.offsets[c];
+        const int64_t ce = (C == 1) ? n : a.offsets[c + 1];
+        const int64_t j0 = cb + (int64_t)k * jc;
+        const int64_t j1 = (j0 + jc < ce) ? j0 + jc : ce;
+        const double eps2 = a.eps2_c ? a.eps2_c[c] : a.eps2;
+        const float eps2f = (float)eps2;
+
+        bool valid[IPL];
+        int pp[IPL], ii[IPL];
+        I64 I[IPL];
+        RUN S[IPL];
+        SumF F[IPL];
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const int pos = slot + q * rows;
+            valid[q] = pos < pcnt;
+            pp[q] = p0 + (valid[q] ? pos : 0);
+            ii[q] = a.idx ? a.idx[pp[q]] : pp[q];
+            const int i = ii[q];
+            I[q].x = a.xp[i]; I[q].y = a.xp[n + i]; I[q].z = a.xp[2 * n + i];
+            I[q].vx = a.vp[i]; I[q].vy = a.vp[n + i]; I[q].vz = a.vp[2 * n + i];
+            S[q].zero();
+            F[q].zero();
+        }
+
+        for (int64_t tb = j0; tb < j1; tb += kTJ) {
+            const int cnt = (int)((j1 - tb) < kTJ ? (j1 - tb) : kTJ);
+            __syncthreads();
+            if (tid < cnt) {
+                const int64_t jg = tb + tid;
+                T.x[tid] = a.xp[jg];
+                T.y[tid] = a.xp[n + jg];
+                T.z[tid] = a.xp[2 * n + jg];
+                if (!POT_ONLY) {
+                    T.vx[tid] = a.vp[jg];
+                    T.vy[tid] = a.vp[n + jg];
+                    T.vz[tid] = a.vp[2 * n + jg];
+                }
+                T.m[tid] = (MT)a.m[jg];
+            }
+            __syncthreads();
+            bool mine = false;
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+                mine = mine || ((int64_t)ii[q] >= tb && (int64_t)ii[q] < tb + cnt);
+            const bool need_mask = __any(mine);
+            if constexpr (POT_ONLY) {
+                if (need_mask) tile_pot<true>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
+                else           tile_pot<false>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
+            } else if constexpr (PREC == 0) {
+                if (need_mask) tile_f64<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+                else           tile_f64<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+            } else {
+                if (need_mask) tile_mixed<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
+                else           tile_mixed<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
+            }
+        }
+
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            double out[7];
+            finalize(S[q], out);
+            if (L > 1) {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) out[r] = shfl_sum(out[r], L);
+            }
+            if (valid[q] && sub == 0) {
+                double* dst = a.partial + (int64_t)k * 7 * na + pp[q];
+                if (POT_ONLY) {
+                    dst[6 * (int64_t)na] = out[6];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) dst[r * (int64_t)na] = out[r];
+                }
+            }
+        }
+    }
+}
+
+// Adds the j-chunk partial sums of every active particle in chunk order.
+template <bool POT_ONLY>
+__global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
+{
+    const int na = a.plan->n_act;
+    const int p = blockIdx.x * kWG + threadIdx.x;
+    if (p >= na) return;
+    int c = 0;
+    if (a.n_clusters > 1) {
+        const int i = a.idx ? a.idx[p] : p;
+        c = upper_bound_i64(a.offsets, a.n_clusters + 1, i) - 1;
+    }
+    const int ch = a.chunks[c];
+    const int64_t st = a.n_act_max;
+    if (POT_ONLY) {
+        double s = 0.0;
+        for (int k = 0; k < ch; ++k) s += a.partial[((int64_t)k * 7 + 6) * na + p];
+        a.pot[p] = s;
+        return;
+    }
+    double s[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) s[q] = 0.0;
+    for (int k = 0; k < ch; ++k) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s[q] += a.partial[((int64_t)k * 7 + q) * na + p];
+    }
+    a.acc[p] = s[0];
+    a.acc[st + p] = s[1];
+    a.acc[2 * st + p] = s[2];
+    if (a.jerk) {
+        a.jerk[p] = s[3];
+        a.jerk[st + p] = s[4];
+        a.jerk[2 * st + p] = s[5];
+    }
+    if (a.pot) a.pot[p] = s[6];
+}
+
+typedef void (*SweepFn)(SweepArgs);
+
+SweepFn sweep_fn(int precision, int variant, bool pot_only)
+{
+    if (pot_only) return sweep_kernel<0, true, 1>;
+    const int ipl = variant == 1 ? 2 : 1;
+    if (precision == 0) return ipl == 2 ? sweep_kernel<0, false, 2> : sweep_kernel<0, false, 1>;
+    if (precision == 1) return ipl == 2 ? sweep_kernel<1, false, 2> : sweep_kernel<1, false, 1>;
+    return ipl == 2 ? sweep_kernel<2, false, 2> : sweep_kernel<2, false, 1>;
+}
+
+}  // namespace
+
+hipError_t launch_force(const SweepArgs& a_in, int precision, int variant,
+                        int grid, bool pot_only, hipStream_t st)
+{
+    SweepArgs a = a_in;
+    a.ipl = (!pot_only && variant == 1) ? 2 : 1;
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
+    hipLaunchKernelGGL(sweep_fn(precision, variant, pot_only), dim3(grid), dim3(kWG), 0, st, a);
+    const int rgrid = (a.n_act_max + kWG - 1) / kWG;
+    if (pot_only) {
+        hipLaunchKernelGGL(reduce_kernel<true>, dim3(rgrid), dim3(kWG), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(reduce_kernel<false>, dim3(rgrid), dim3(kWG), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hm
+
+namespace hm {
+
+// Resident workgroups per compute unit of a sweep kernel (from its register
+// and LDS use); the default persistent grid is this times the CU count.
+int sweep_occupancy(int precision, int variant, bool pot_only)
+{
+    int nb = 0;
+    const void* f = reinterpret_cast<const void*>(sweep_fn(precision, variant, pot_only));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWG, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 4;
+    }
+    return nb;
+}
+
+}  // namespace hm

@@ -1,0 +1,324 @@
+"""GPU block-step stages vs the oracle, through the C ABI: selection
+(bit-exact), predictor, corrector + next step, first step, energy, one-step
+lockstep integration, graph replay vs eager, ensembles vs per-cluster."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import check_fp64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TB = 20
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1104_2700_amd import hermite
+    return hermite
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda", dtype=dtype) if dtype else t.cuda()
+
+
+def _near_boundary(crit, rel=1e-7):
+    """True where a criterion lies within rel of a power of two."""
+    crit = np.asarray(crit, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l2 = np.log2(crit)
+    return np.abs(l2 - np.rint(l2)) < rel / np.log(2)
+
+
+@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 70000])
+def test_select_bit_exact(H, ctx, n):
+    from oracle import oracle as O
+    from paper_1104_2700_amd import inputs
+    T = 3 << 14
+    t, dt = inputs.synced_block_times(n, n, TB, 3, 14, T)
+    s = H.State(np.zeros((3, n)), np.zeros((3, n)), np.ones(n), TB)
+    s.t.copy_(_dev(t)); s.dt.copy_(_dev(dt))
+    idx = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Td = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.select_block(s, idx, na, Td)
+    torch.cuda.synchronize()
+    T_ref, idx_ref = O.select(t, dt)
+    assert int(Td.item()) == T_ref
+    k = int(na.item())
+    assert k == idx_ref.shape[0]
+    assert np.array_equal(idx[:k].cpu().numpy(), idx_ref)
+    # a block time past T_end selects nothing
+    ctx.select_block(s, idx, na, Td, T_end=T_ref - 1)
+    torch.cuda.synchronize()
+    assert int(na.item()) == 0 and int(Td.item()) == T_ref
+
+
+def test_predict_parity(H, ctx):
+    from oracle import oracle as O
+    from paper_1104_2700_amd import inputs
+    n = 3001
+    rng = np.random.default_rng(4)
+    x, v, a, j = rng.normal(size=(4, 3, n))
+    T = 5 << 12
+    t, dt = inputs.synced_block_times(n, 9, TB, 3, 20, T)
+    s = H.State(x, v, np.ones(n), TB)
+    s.a.copy_(_dev(a)); s.j.copy_(_dev(j)); s.t.copy_(_dev(t))
+    ctx.predict(s, T_host=T)
+    torch.cuda.synchronize()
+    xp, vp = O.predict(x, v, a, j, t, T, TB)
+    scale_x = np.abs(x) + np.abs(v) + np.abs(a) + np.abs(j)
+    assert np.all(np.abs(s.xp.cpu().numpy() - xp) <= 4e-16 * scale_x)
+    assert np.all(np.abs(s.vp.cpu().numpy() - vp) <= 4e-16 * scale_x)
+    # device block time and a zero active count (no-op)
+    Td = torch.tensor([T], dtype=torch.int64, device="cuda")
+    s.xp.zero_()
+    ctx.predict(s, T_dev=Td)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(s.xp.cpu().numpy() - xp) <= 4e-16 * scale_x)
+    s.xp.zero_()
+    ctx.predict(s, T_dev=Td, n_act_dev=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.all(s.xp == 0)
+
+
+def test_correct_parity(H, ctx):
+    """Corrector, a0/j0 update, t and the next step for a random active list
+    (inputs are random but consistent: t_i + dt_i = T)."""
+    from oracle import oracle as O
+    n = 2000
+    rng = np.random.default_rng(5)
+    T = 1 << 15
+    k = rng.integers(5, 15, size=n)
+    dt = (np.int64(1) << (TB - k)).astype(np.int64)
+    t = (T - dt).astype(np.int64)
+    x, v, a0, j0 = rng.normal(size=(4, 3, n))
+    ostate = O.new_state(x, v, np.ones(n), TB)
+    ostate["a"][...] = a0; ostate["j"][...] = j0
+    ostate["t"][...] = t; ostate["dt"][...] = dt
+    xp, vp = O.predict(x, v, a0, j0, t, T, TB)
+    idx = np.sort(rng.choice(n, 700, replace=False)).astype(np.int32)
+    h = (dt[idx] * 2.0**-TB)[None]
+    a1 = a0[:, idx] + j0[:, idx] * h + rng.normal(size=(3, 700)) * h * h
+    j1 = j0[:, idx] + rng.normal(size=(3, 700)) * h
+    p1 = rng.normal(size=700)
+    s = H.State(x, v, np.ones(n), TB)
+    s.a.copy_(_dev(a0)); s.j.copy_(_dev(j0)); s.t.copy_(_dev(t)); s.dt.copy_(_dev(dt))
+    s.xp.copy_(_dev(xp)); s.vp.copy_(_dev(vp))
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    crit = torch.zeros(700, dtype=torch.float64, device="cuda")
+    ctx.correct(s, _dev(idx), _dev(a1), _dev(j1), _dev(p1), params, T_host=T, crit_out=crit)
+    torch.cuda.synchronize()
+    crit_ref = np.zeros(700)
+    O.correct(ostate, idx, T, xp, vp, a1, j1, p1, 0.02, 0, 3, 20, crit_out=crit_ref)
+    g = s.to_numpy()
+    sc = np.abs(xp) + 1.0
+    assert np.all(np.abs(g["x"] - ostate["x"]) <= 1e-14 * sc)
+    assert np.all(np.abs(g["v"] - ostate["v"]) <= 1e-14 * (np.abs(vp) + 1.0))
+    assert np.array_equal(g["a"], ostate["a"]) and np.array_equal(g["j"], ostate["j"])
+    assert np.array_equal(g["t"], ostate["t"]) and np.array_equal(g["pot"], ostate["pot"])
+    c = crit.cpu().numpy()
+    assert np.allclose(c, crit_ref, rtol=1e-9)
+    mism = g["dt"] != ostate["dt"]
+    assert np.all(_near_boundary(crit_ref[np.searchsorted(idx, np.nonzero(mism)[0])], 1e-9)) \
+        if mism.any() else True
+
+
+def _c1_setup(H, n=1024, seed=1, eps=1.0 / 64):
+    from paper_1104_2700_amd import inputs
+    x, v, m = inputs.plummer(n, seed)
+    return x, v, m, eps * eps
+
+
+def test_initialize_and_energy(H, ctx):
+    from oracle import oracle as O
+    x, v, m, eps2 = _c1_setup(H)
+    n = m.shape[0]
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s = H.State(x, v, m, TB)
+    ctx.initialize(s, eps2, params, H.FP64)
+    e = ctx.energy(s, eps2)
+    torch.cuda.synchronize()
+    ost = O.new_state(x, v, m, TB)
+    O.initialize(ost, eps2, 0.02, 0, 3, 20)
+    g = s.to_numpy()
+    _, _, _, cond = O.force(x, v, m, np.arange(n, dtype=np.int32), eps2, with_cond=True)
+    check_fp64("a0", g["a"], ost["a"], cond[0], n)
+    check_fp64("j0", g["j"], ost["j"], cond[1], n)
+    assert np.all(g["t"] == 0)
+    crit = 0.02 * np.linalg.norm(ost["a"], axis=0) / np.linalg.norm(ost["j"], axis=0)
+    mism = g["dt"] != ost["dt"]
+    assert np.all(_near_boundary(crit[mism], 1e-9))
+    K, W = O.energy(x, v, m, eps2)
+    Kg, Wg = e[0].tolist()
+    assert Kg == pytest.approx(K, rel=1e-14)
+    assert Wg == pytest.approx(W, rel=1e-13)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lockstep_block_steps(H, ctx, prec):
+    """One block step at a time: the oracle takes the GPU's pre-step state
+    and both advance; post-step states must agree (FP64: forces to 1e-13,
+    positions to ~1e-15; mixed: to the mixed tolerance), with identical
+    block times and active lists."""
+    from oracle import oracle as O
+    x, v, m, eps2 = _c1_setup(H)
+    n = m.shape[0]
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s = H.State(x, v, m, TB)
+    ctx.initialize(s, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    dt_mism = 0
+    n_steps = 40
+    for step in range(n_steps):
+        pre = s.to_numpy()
+        ost = {k: (pre[k].copy() if isinstance(pre[k], np.ndarray) else pre[k]) for k in pre}
+        T, idx = O.select(ost["t"], ost["dt"])
+        xp, vp = O.predict(ost["x"], ost["v"], ost["a"], ost["j"], ost["t"], T, TB)
+        a1, j1, p1 = O.force(xp, vp, m, idx, eps2)
+        crit_ref = np.zeros(idx.shape[0])
+        O.correct(ost, idx, T, xp, vp, a1, j1, p1, 0.02, 0, 3, 20, crit_out=crit_ref)
+        ctx.step(s, eps2, params, prec)
+        cnt = ctx.counters()
+        g = s.to_numpy()
+        assert cnt["T"] == T and cnt["n_act"] == idx.shape[0]
+        assert np.array_equal(g["t"], ost["t"])
+        rel_x = np.abs(g["x"] - ost["x"]).max() / np.abs(ost["x"]).max()
+        assert rel_x < (1e-14 if prec == 0 else 1e-9), rel_x
+        ea = np.linalg.norm(g["a"][:, idx] - ost["a"][:, idx], axis=0) / np.linalg.norm(ost["a"][:, idx], axis=0)
+        assert ea.max() < (1e-12 if prec == 0 else 2e-6), ea.max()
+        mism = g["dt"] != ost["dt"]
+        if mism.any():
+            pos = np.searchsorted(idx, np.nonzero(mism)[0])
+            if prec == 0:
+                assert np.all(_near_boundary(crit_ref[pos], 1e-6))
+            ratio = g["dt"][mism] / ost["dt"][mism]
+            assert np.all((ratio == 2) | (ratio == 0.5))
+            dt_mism += int(mism.sum())
+            # continue from the oracle's decision so the runs stay in step
+            s.dt.copy_(_dev(ost["dt"]))
+    if prec == 0:
+        assert dt_mism <= 2
+
+
+def test_graph_replay_matches_eager(H, ctx):
+    x, v, m, eps2 = _c1_setup(H, n=2048, seed=11)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, H.FP64)
+    sa, sb = s0.clone(), s0.clone()
+    for _ in range(30):
+        ctx.step(sa, eps2, params, H.MIXED, use_graph=False)
+    for k in range(30):
+        ctx.step(sb, eps2, params, H.MIXED, use_graph=True)
+        if k % 7 == 3:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+        assert torch.equal(getattr(sa, key), getattr(sb, key)), key
+
+
+def test_run_c1_energy_and_oracle(H, ctx):
+    """Plummer N = 1024, eps = 1/64, eta = 0.02, t = 0 -> 0.125 (FP64):
+    graph-replayed run, energy conserved like the oracle's run."""
+    from oracle import oracle as O
+    x, v, m, eps2 = _c1_setup(H)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    T_end = 1 << (TB - 3)
+    s = H.State(x, v, m, TB)
+    ctx.initialize(s, eps2, params, H.FP64)
+    e0 = ctx.energy(s, eps2)[0].sum().item()
+    steps, inter = ctx.run(s, eps2, params, T_end, H.FP64, use_graph=True, sync_every=32)
+    e1 = ctx.energy(s, eps2)[0].sum().item()
+    g = s.to_numpy()
+    assert np.all(g["t"] == T_end)
+    ost = O.new_state(x, v, m, TB)
+    stats = O.run(ost, T_end, eps2, 0.02, 0, 3, 20)
+    K0, W0 = O.energy(x, v, m, eps2)
+    K1, W1 = O.energy(ost["x"], ost["v"], m, eps2)
+    d_gpu = abs(e1 - e0) / abs(e0)
+    d_ora = abs((K1 + W1) - (K0 + W0)) / abs(K0 + W0)
+    assert d_gpu < 1e-6 and d_ora < 1e-6
+    assert abs(steps - stats["steps"]) <= 0.02 * stats["steps"]
+    assert np.abs(g["x"] - ost["x"]).max() < 1e-6
+
+
+def test_ensemble_force_and_lockstep(H, ctx):
+    """Clusters of uneven size (including a lone particle) in one state:
+    per-cluster sums and softening, and a few lockstep block steps."""
+    from oracle import oracle as O
+    from paper_1104_2700_amd import inputs
+    sizes = [300, 1000, 64, 1, 2000, 513]
+    xs, vs, ms = [], [], []
+    for c, nc in enumerate(sizes):
+        x, v, m = inputs.plummer(nc, 500 + c)
+        xs.append(x); vs.append(v); ms.append(m)
+    x = np.concatenate(xs, 1); v = np.concatenate(vs, 1); m = np.concatenate(ms)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps2 = (4.0 / np.maximum(np.array(sizes, float), 64)) ** 2
+    cl = H.Clusters(off, eps2)
+    s = H.State(x, v, m, TB)
+    s.xp.copy_(s.x); s.vp.copy_(s.v)
+    n = m.shape[0]
+    acc, jrk, pot = ctx.force_jerk(s, None, 0.0, H.FP64, clusters=cl)
+    torch.cuda.synchronize()
+    A, J, P = acc.cpu().numpy(), jrk.cpu().numpy(), pot.cpu().numpy()
+    for c in range(len(sizes)):
+        lo, hi = off[c], off[c + 1]
+        ids = np.arange(lo, hi, dtype=np.int32)
+        ra, rj, rp, cond = O.force(x, v, m, ids, eps2[c], j_range=(lo, hi), with_cond=True)
+        check_fp64("acc%d" % c, A[:, lo:hi], ra, cond[0], hi - lo)
+        check_fp64("jerk%d" % c, J[:, lo:hi], rj, cond[1], hi - lo)
+    # energies per cluster
+    e = ctx.energy(s, 0.0, clusters=cl).cpu().numpy()
+    for c in range(len(sizes)):
+        lo, hi = off[c], off[c + 1]
+        K, W = O.energy(x[:, lo:hi], v[:, lo:hi], m[lo:hi], eps2[c])
+        assert e[c, 0] == pytest.approx(K, rel=1e-13)
+        assert e[c, 1] == pytest.approx(W, rel=1e-12, abs=1e-300)
+    # lockstep: the union of clusters on one timeline equals each cluster
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    ctx.initialize(s, 0.0, params, H.FP64, clusters=cl)
+    torch.cuda.synchronize()
+    for _ in range(10):
+        pre = s.to_numpy()
+        T, idx = O.select(pre["t"], pre["dt"])
+        ctx.step(s, 0.0, params, H.FP64, clusters=cl)
+        g = s.to_numpy()
+        for c in range(len(sizes)):
+            lo, hi = off[c], off[c + 1]
+            act = idx[(idx >= lo) & (idx < hi)]
+            if act.size == 0:
+                assert np.array_equal(g["x"][:, lo:hi], pre["x"][:, lo:hi])
+                continue
+            sub = {k: (pre[k][..., lo:hi].copy() if isinstance(pre[k], np.ndarray) else pre[k])
+                   for k in pre}
+            xp, vp = O.predict(sub["x"], sub["v"], sub["a"], sub["j"], sub["t"], T, TB)
+            la = (act - lo).astype(np.int32)
+            a1, j1, p1 = O.force(xp, vp, sub["m"], la, eps2[c])
+            O.correct(sub, la, T, xp, vp, a1, j1, p1, 0.02, 0, 3, 20)
+            assert np.abs(g["x"][:, lo:hi] - sub["x"]).max() <= 1e-14 * (np.abs(sub["x"]).max() + 1)
+            assert np.array_equal(g["t"][lo:hi], sub["t"])
+
+
+def test_counters_and_clamped(H, ctx):
+    """A hard binary forces steps below 2^-k_max: the clamped count rises."""
+    from paper_1104_2700_amd import inputs
+    x, v, m = inputs.kepler_pair(1e-2, 0.5, 0.5, 0.5, 0.0)
+    s = H.State(x, v, m, TB)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 8)
+    c0 = ctx.counters()
+    ctx.initialize(s, 0.0, params, H.FP64)
+    ctx.run(s, 0.0, params, 1 << (TB - 3), H.FP64, use_graph=False, sync_every=8)
+    c1 = ctx.counters()
+    assert c1["clamped"] > c0["clamped"]
+    assert c1["steps"] > c0["steps"]
