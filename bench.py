@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -56,6 +57,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape")
+    ap.add_argument("--tuning-cache", default=os.path.join(tempfile.gettempdir(),
+                                                           "hermite_tuning.json"),
+                    help="autotuner cache: loaded if it has this size, else written")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -96,12 +100,12 @@ def main():
     precs = [p for p in args.precisions.split(",") if p]
     for pname in precs:
         prec = H.PRECISIONS[pname]
-        if not args.no_autotune:
+        if not args.no_autotune and not ctx.load_tuning(args.tuning_cache, prec, N, N):
             # pick the sweep's launch shape for this size (untimed set-up)
             ts = base.clone()
             ts.xp.copy_(ts.x)
             ts.vp.copy_(ts.v)
-            ctx.autotune(ts, eps2, prec, N)
+            ctx.autotune(ts, eps2, prec, N, cache_path=args.tuning_cache)
             del ts
         tuning = ctx.get_tuning(prec).as_dict()
         s = base.clone()

@@ -59,7 +59,8 @@ struct SweepArgs {
 };
 
 // Sweep launchers (sweep.hip).  precision: 0 fp64, 1 mixed, 2 mixed-2f.
-// variant: 0 one active particle per lane, 1 two per lane.
+// variant bit 0: two active particles per lane (else one); bit 1: split
+// FP32 hi/lo differences in the mixed precisions.
 // pot_only: the energy sweep (FP64, potential only).
 hipError_t launch_force(const SweepArgs& a, int precision, int variant,
                         int grid, bool pot_only, hipStream_t st);

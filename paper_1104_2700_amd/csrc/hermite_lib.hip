@@ -643,7 +643,7 @@ int hermite_set_tuning(hermite_ctx* c, int precision, const hermite_tuning* in)
     if (!c || !in) return fail(HERMITE_EINVAL, "null argument");
     CHECK(check_precision(precision));
     if (in->wg_per_cu < 1 || in->wg_per_cu > 64 || in->target_lanes < kWG ||
-        in->min_j_per_lane < 1 || in->variant < 0 || in->variant > 1)
+        in->min_j_per_lane < 1 || in->variant < 0 || in->variant > 3)
         return fail(HERMITE_EINVAL, "tuning out of range");
     c->tuning[precision] = *in;
     return HERMITE_OK;
@@ -814,7 +814,8 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, double eps2, int pr
         for (int q = 0; q < 3; ++q) limit[q] = std::max(tol, 1.5 * e[q]);
         const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{64}
                                                    : std::vector<int>{16, 32, 64, 128};
-        for (int var = 0; var <= 1 && rc == HERMITE_OK; ++var) {
+        const int nvar = precision == HERMITE_FP64 ? 2 : 4;
+        for (int var = 0; var < nvar && rc == HERMITE_OK; ++var) {
             for (int w = 2; w <= 8 && rc == HERMITE_OK; ++w) {
                 for (int f : {1, 2, 4}) {
                     for (int mj : mjs) {

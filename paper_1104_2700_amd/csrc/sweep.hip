@@ -306,6 +306,49 @@ __device__ __forceinline__ void pair_mixed(const I64& I, float eps2f, double xj,
     S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
 }
 
+// Split form of the mixed pair term: every FP64 coordinate c is held as
+// hi = fl32(c), lo = fl32(c - hi), and the difference is formed in FP32 as
+// (hi_j - hi_i) + (lo_j - lo_i).  For a close pair the hi difference is
+// exact (Sterbenz), so the result carries the same FP32 rounding of the
+// FP64 difference as the cast form, at three FP32 operations instead of
+// an FP64 subtraction and a conversion.
+struct I32S {  // i-particle, split coordinates
+    float xh, xl, yh, yl, zh, zl, vxh, vxl, vyh, vyl, vzh, vzl;
+};
+
+__device__ __forceinline__ void split(double c, float& h, float& l)
+{
+    h = (float)c;
+    l = (float)(c - (double)h);
+}
+
+template <bool MASK>
+__device__ __forceinline__ void pair_split(const I32S& I, float eps2f, const float* J,
+                                           float mj, bool self, SumF& S)
+{
+    const float dx = (J[0] - I.xh) + (J[1] - I.xl);
+    const float dy = (J[2] - I.yh) + (J[3] - I.yl);
+    const float dz = (J[4] - I.zh) + (J[5] - I.zl);
+    const float dvx = (J[6] - I.vxh) + (J[7] - I.vxl);
+    const float dvy = (J[8] - I.vyh) + (J[9] - I.vyl);
+    const float dvz = (J[10] - I.vzh) + (J[11] - I.vzl);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    if (MASK) ri = self ? 0.0f : ri;
+    const float mr = mj * ri;
+    const float ri2 = ri * ri;
+    const float mr3 = mr * ri2;
+    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+    const float b3 = (rv * ri2) * 3.0f;
+    S.pp += mr;
+    S.ax = fmaf(mr3, dx, S.ax);
+    S.ay = fmaf(mr3, dy, S.ay);
+    S.az = fmaf(mr3, dz, S.az);
+    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
+    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
+    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+}
+
 __device__ __forceinline__ void flush(SumF& f, SumD& d)
 {
     d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
@@ -327,6 +370,13 @@ template <typename MT>
 struct Tile {
     double x[kTJ], y[kTJ], z[kTJ], vx[kTJ], vy[kTJ], vz[kTJ];
     MT m[kTJ];
+};
+
+// LDS tile of j-particles with split coordinates: c[k][j] for the twelve
+// hi/lo words (x, y, z, vx, vy, vz), and the FP32 mass.
+struct TileS {
+    float c[12][kTJ];
+    float m[kTJ];
 };
 
 // ---- tile loops ---------------------------------------------------------
@@ -397,6 +447,33 @@ __device__ __forceinline__ void tile_mixed(const Tile<float>& T, int cnt, int su
     }
 }
 
+template <bool MASK, int IPL, typename RUN>
+__device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int L,
+                                           int64_t tb, const int (&ii)[IPL],
+                                           const I32S (&I)[IPL], float eps2f,
+                                           SumF (&f)[IPL], RUN (&S)[IPL])
+{
+    constexpr int kUnroll = IPL == 1 ? 4 : 2;
+    const int step = kMixedK * L;
+    for (int jb = 0; jb < cnt; jb += step) {
+        const int je = (jb + step < cnt) ? jb + step : cnt;
+#pragma unroll kUnroll
+        for (int jj = jb + sub; jj < je; jj += L) {
+            float J[12];
+#pragma unroll
+            for (int w = 0; w < 12; ++w) J[w] = T.c[w][jj];
+            const float mj = T.m[jj];
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
+                pair_split<MASK>(I[q], eps2f, J, mj, self, f[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+    }
+}
+
 __device__ __forceinline__ double shfl_sum(double v, int L)
 {
     for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
@@ -425,12 +502,14 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[7])
 //   IPL: active particles per lane (1 or 2).  Lane `slot` of an item holds
 //   the item's particles slot, slot + kWG/L, ...
 // ------------------------------------------------------------------------
-template <int PREC, bool POT_ONLY, int IPL>
+template <int PREC, bool POT_ONLY, int IPL, bool SPLIT>
 __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
 {
+    static_assert(!SPLIT || (PREC != 0 && !POT_ONLY), "split form is mixed-only");
     using MT = typename std::conditional<PREC == 0, double, float>::type;
     using RUN = typename std::conditional<PREC == 2, Sum2F, SumD>::type;
-    __shared__ Tile<MT> T;
+    using TT = typename std::conditional<SPLIT, TileS, Tile<MT>>::type;
+    __shared__ TT T;
     __shared__ int32_t s_item;
 
     SweepPlan* P = a.plan;
@@ -472,6 +551,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         bool valid[IPL];
         int pp[IPL], ii[IPL];
         I64 I[IPL];
+        I32S IS[IPL];
         RUN S[IPL];
         SumF F[IPL];
 #pragma unroll
@@ -483,6 +563,14 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             const int i = ii[q];
             I[q].x = a.xp[i]; I[q].y = a.xp[n + i]; I[q].z = a.xp[2 * n + i];
             I[q].vx = a.vp[i]; I[q].vy = a.vp[n + i]; I[q].vz = a.vp[2 * n + i];
+            if constexpr (SPLIT) {
+                split(I[q].x, IS[q].xh, IS[q].xl);
+                split(I[q].y, IS[q].yh, IS[q].yl);
+                split(I[q].z, IS[q].zh, IS[q].zl);
+                split(I[q].vx, IS[q].vxh, IS[q].vxl);
+                split(I[q].vy, IS[q].vyh, IS[q].vyl);
+                split(I[q].vz, IS[q].vzh, IS[q].vzl);
+            }
             S[q].zero();
             F[q].zero();
         }
@@ -492,15 +580,24 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             __syncthreads();
             if (tid < cnt) {
                 const int64_t jg = tb + tid;
-                T.x[tid] = a.xp[jg];
-                T.y[tid] = a.xp[n + jg];
-                T.z[tid] = a.xp[2 * n + jg];
-                if (!POT_ONLY) {
-                    T.vx[tid] = a.vp[jg];
-                    T.vy[tid] = a.vp[n + jg];
-                    T.vz[tid] = a.vp[2 * n + jg];
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        split(a.xp[d * n + jg], T.c[2 * d][tid], T.c[2 * d + 1][tid]);
+                        split(a.vp[d * n + jg], T.c[6 + 2 * d][tid], T.c[7 + 2 * d][tid]);
+                    }
+                    T.m[tid] = (float)a.m[jg];
+                } else {
+                    T.x[tid] = a.xp[jg];
+                    T.y[tid] = a.xp[n + jg];
+                    T.z[tid] = a.xp[2 * n + jg];
+                    if (!POT_ONLY) {
+                        T.vx[tid] = a.vp[jg];
+                        T.vy[tid] = a.vp[n + jg];
+                        T.vz[tid] = a.vp[2 * n + jg];
+                    }
+                    T.m[tid] = (MT)a.m[jg];
                 }
-                T.m[tid] = (MT)a.m[jg];
             }
             __syncthreads();
             bool mine = false;
@@ -514,6 +611,9 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             } else if constexpr (PREC == 0) {
                 if (need_mask) tile_f64<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
                 else           tile_f64<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+            } else if constexpr (SPLIT) {
+                if (need_mask) tile_split<true, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
+                else           tile_split<false, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
             } else {
                 if (need_mask) tile_mixed<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
                 else           tile_mixed<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
@@ -581,13 +681,21 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
 
 typedef void (*SweepFn)(SweepArgs);
 
+// variant: bit 0 -> two active particles per lane; bit 1 -> split
+// differences (mixed precisions only; FP64 ignores it).
 SweepFn sweep_fn(int precision, int variant, bool pot_only)
 {
-    if (pot_only) return sweep_kernel<0, true, 1>;
-    const int ipl = variant == 1 ? 2 : 1;
-    if (precision == 0) return ipl == 2 ? sweep_kernel<0, false, 2> : sweep_kernel<0, false, 1>;
-    if (precision == 1) return ipl == 2 ? sweep_kernel<1, false, 2> : sweep_kernel<1, false, 1>;
-    return ipl == 2 ? sweep_kernel<2, false, 2> : sweep_kernel<2, false, 1>;
+    if (pot_only) return sweep_kernel<0, true, 1, false>;
+    const bool two = (variant & 1) != 0;
+    const bool spl = (variant & 2) != 0;
+    if (precision == 0)
+        return two ? sweep_kernel<0, false, 2, false> : sweep_kernel<0, false, 1, false>;
+    if (precision == 1) {
+        if (spl) return two ? sweep_kernel<1, false, 2, true> : sweep_kernel<1, false, 1, true>;
+        return two ? sweep_kernel<1, false, 2, false> : sweep_kernel<1, false, 1, false>;
+    }
+    if (spl) return two ? sweep_kernel<2, false, 2, true> : sweep_kernel<2, false, 1, true>;
+    return two ? sweep_kernel<2, false, 2, false> : sweep_kernel<2, false, 1, false>;
 }
 
 }  // namespace
@@ -596,7 +704,7 @@ hipError_t launch_force(const SweepArgs& a_in, int precision, int variant,
                         int grid, bool pot_only, hipStream_t st)
 {
     SweepArgs a = a_in;
-    a.ipl = (!pot_only && variant == 1) ? 2 : 1;
+    a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
     hipLaunchKernelGGL(sweep_fn(precision, variant, pot_only), dim3(grid), dim3(kWG), 0, st, a);
     const int rgrid = (a.n_act_max + kWG - 1) / kWG;

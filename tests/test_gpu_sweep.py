@@ -60,10 +60,40 @@ def test_fp64_sweep_parity(H, ctx, n, n_act):
     check_fp64("pot", pot.cpu().numpy()[None], rp[None], cond[2], n)
 
 
+@pytest.fixture
+def variant(H, ctx, request):
+    """Installs launch-shape variant `request.param` for every precision
+    (bit 0: two particles per lane, bit 1: split FP32 differences)."""
+    saved = [ctx.get_tuning(p) for p in range(3)]
+    for p in range(3):
+        t = ctx.get_tuning(p)
+        t.variant = request.param
+        ctx.set_tuning(p, t)
+    yield request.param
+    for p in range(3):
+        ctx.set_tuning(p, saved[p])
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3], indirect=True)
+@pytest.mark.parametrize("n,n_act", [(3, 3), (300, 300), (1023, 1000), (2049, 9)])
+def test_fp64_sweep_parity_variants(H, ctx, variant, n, n_act):
+    from oracle import oracle as O
+    s, x, v, m = _state(H, n, 300 + n)
+    eps2 = (4.0 / max(n, 64)) ** 2
+    idx = _idx(n, n_act, n + 11)
+    acc, jrk, pot = ctx.force_jerk(s, torch.from_numpy(idx).cuda(), eps2, H.FP64)
+    torch.cuda.synchronize()
+    ra, rj, rp, cond = O.force(x, v, m, idx, eps2, with_cond=True)
+    check_fp64("acc", acc.cpu().numpy(), ra, cond[0], n)
+    check_fp64("jerk", jrk.cpu().numpy(), rj, cond[1], n)
+    check_fp64("pot", pot.cpu().numpy()[None], rp[None], cond[2], n)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3], indirect=True)
 @pytest.mark.parametrize("prec", ["mixed", "mixed2f"])
 @pytest.mark.parametrize("n,n_act", [(1, 1), (64, 7), (257, 257), (1024, 1024),
                                      (4097, 65), (5000, 1)])
-def test_mixed_sweep_parity(H, ctx, prec, n, n_act):
+def test_mixed_sweep_parity(H, ctx, variant, prec, n, n_act):
     from oracle import oracle as O
     s, x, v, m = _state(H, n, 200 + n)
     eps2 = (4.0 / max(n, 64)) ** 2
@@ -132,8 +162,9 @@ def test_zero_softening_two_body(H, ctx):
         assert np.allclose(pot.cpu().numpy(), rp, rtol=tol, atol=0)
 
 
+@pytest.mark.parametrize("variant", [1, 3], indirect=True)
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_full_sweep_65536_sampled(H, ctx, prec):
+def test_full_sweep_65536_sampled(H, ctx, variant, prec):
     """The full N = 65536 Plummer sweep in the benchmark's launch shape,
     checked on 1024 sampled particles against the oracle, plus the
     momentum invariants over all particles."""
