@@ -217,20 +217,28 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
                  void* stream);
 
 /* Repeat hermite_step until every particle reaches T_end (ticks; must be
- * a multiple of 2^(tick_bits - k_min)).  The host reads the device block
- * time once every sync_every steps.  steps_out / interactions_out (host,
- * may be NULL) receive the block-step count and the number of pair
- * interactions (sum over steps of sum_i n_c(i)) of this call. */
+ * a multiple of 2^(tick_bits - k_min)), or until max_steps steps have been
+ * launched (max_steps <= 0: no limit; the call can then be repeated to
+ * continue).  The host reads the device block time once every sync_every
+ * steps.  steps_out / interactions_out (host, may be NULL) receive the
+ * block-step count and the number of pair interactions (sum over steps of
+ * sum_i n_c(i)) of this call; done_out (host, may be NULL) is set to 1 when
+ * every particle has reached T_end. */
 int hermite_run(hermite_ctx* ctx, const hermite_state* s,
                 const hermite_clusters* cl, double eps2, int precision,
                 const hermite_dt_params* p, int64_t T_end, int use_graph,
-                int32_t sync_every, int64_t* steps_out,
-                int64_t* interactions_out, void* stream);
+                int32_t sync_every, int64_t max_steps, int64_t* steps_out,
+                int64_t* interactions_out, int32_t* done_out, void* stream);
 
 /* Cumulative device counters since creation (synchronises `stream`):
  * out[0] block steps, out[1] interactions, out[2] clamped steps,
  * out[3] last block time T, out[4] last n_act. */
 int hermite_counters(hermite_ctx* ctx, int64_t out[5], void* stream);
+
+/* Histogram of the active-block sizes of every block step since creation
+ * (synchronises `stream`): out[0] counts steps with n_act = 0 past T_end,
+ * out[b] for b >= 1 counts steps with 2^(b-1) <= n_act < 2^b. */
+int hermite_block_histogram(hermite_ctx* ctx, int64_t out[33], void* stream);
 
 /* ---- launch shape and autotuner ------------------------------------------ */
 
@@ -238,15 +246,19 @@ int hermite_get_tuning(hermite_ctx* ctx, int precision, hermite_tuning* out);
 int hermite_set_tuning(hermite_ctx* ctx, int precision,
                        const hermite_tuning* in);
 
-/* Time candidate launch shapes of the sweep for this state, precision and
- * active count (the first n_act particles, or all for n_act = n) with HIP
- * events, keep the fastest whose results agree with the default shape
- * (FP64: 1e-13 relative, mixed: 1e-6), install it in the context and,
- * if cache_path is non-NULL, merge it into that JSON file keyed by
- * device architecture, precision and size bucket.  Synchronises. */
+/* Time candidate launch shapes (variant, workgroups per CU, j-split
+ * target, minimum j-run) of the sweep for this state (and clusters, may be
+ * NULL), precision and active count (the first n_act particles) with HIP
+ * events at the predicted positions s->xp, s->vp, and keep the fastest
+ * whose results stay as close to an FP64 sweep as the precision allows
+ * (FP64: 1e-13 relative; mixed: 1e-6 or 1.5 times the default shape's
+ * deviation, whichever is larger).  Installs it in the context and, if
+ * cache_path is non-NULL, merges it into that JSON file keyed by device
+ * architecture, HIP version, precision and power-of-two size buckets of
+ * n and n_act.  Synchronises. */
 int hermite_autotune(hermite_ctx* ctx, const hermite_state* s,
-                     double eps2, int precision, int32_t n_act,
-                     const char* cache_path, void* stream);
+                     const hermite_clusters* cl, double eps2, int precision,
+                     int32_t n_act, const char* cache_path, void* stream);
 
 /* Load tunings from a cache written by hermite_autotune for this device
  * and the given n / n_act bucket; returns HERMITE_OK if an entry was

@@ -12,6 +12,11 @@ namespace hm {
 constexpr int kWG = 256;
 constexpr int kTJ = 256;
 
+// Device counters: [0] block steps, [1] interactions, [2] clamped steps,
+// [3] last block time, [4] last n_act, [kHistBase + b] block-size histogram.
+constexpr int kHistBase = 8;
+constexpr int kCounters = kHistBase + 33;
+
 // Shape of one force sweep, decided on the device from the active count
 // (so that a captured graph adapts to every block size).
 struct SweepPlan {
@@ -57,6 +62,16 @@ struct SweepArgs {
     double* jerk;              // [3][n_act_max] or null
     double* pot;               // [n_act_max] or null
 };
+
+// Grid of the grid-stride reduce/correct kernels: enough blocks for one
+// wave per particle (the many-chunk mode), capped at 4096 blocks; the
+// kernels loop over the rest, and the one-thread-per-particle mode uses
+// the same grid.
+inline int reduce_grid(int64_t n_act_max)
+{
+    const int64_t g = (n_act_max + (kWG / 64) - 1) / (kWG / 64);
+    return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
 
 // Sweep launchers (sweep.hip).  precision: 0 fp64, 1 mixed, 2 mixed-2f.
 // variant bit 0: two active particles per lane (else one); bit 1: split
@@ -109,6 +124,19 @@ struct CorrectArgs {
 };
 
 hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
+
+// Fused block-step stages: selection + prediction of every particle + the
+// sweep plan in three launches (the last one fused), and the corrector
+// with the fixed-order reduction of the sweep's partial sums.
+hipError_t launch_step_select(int64_t n, int tick_bits, const double* x, const double* v,
+                              const double* a, const double* j, double* xp, double* vp,
+                              const int64_t* t, const int64_t* dt, int64_t T_end,
+                              int32_t* idx, int32_t* n_act, int64_t* T, int64_t* block_min,
+                              int32_t* block_cnt, int64_t* counters, uint32_t* ticket,
+                              const SweepArgs& sa, hipStream_t st);
+hipError_t launch_sweep_only(const SweepArgs& a, int precision, int variant, int grid,
+                             hipStream_t st);
+hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);
 
 hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,
                           const double* j, int64_t* t, int64_t* dt,

@@ -69,7 +69,7 @@ struct hermite_ctx {
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     Buf sel_min, sel_cnt;
-    Buf step_idx, step_na, step_T, step_out, phi, counters;
+    Buf step_idx, step_na, step_T, step_out, phi, counters, ticket;
     std::vector<GraphEntry> graphs;
 };
 
@@ -163,17 +163,18 @@ int check_dt(const hermite_dt_params* p, int tick_bits)
 }
 
 // Default launch shape: two active particles per lane (variant 1), five
-// persistent workgroups per CU, and a j-split that gives every resident
-// lane work (twice over for FP64, whose longer dependency chains gain from
-// more, smaller items).  Chosen from a sweep of these parameters at
-// N = 65536 on gfx950; hermite_autotune refines it per size.
+// persistent workgroups per CU, and a work split aiming at one item per
+// workgroup of the grid.
+// Chosen from a sweep of these parameters over active counts 256 ... 65536
+// at N = 65536 on gfx950; hermite_autotune refines it per size.
 hermite_tuning default_tuning(const hermite_ctx* c, int precision)
 {
+    (void)precision;
     hermite_tuning t;
     t.variant = 1;
     t.wg_per_cu = 5;
-    t.target_lanes = c->n_cu * t.wg_per_cu * kWG * (precision == HERMITE_FP64 ? 2 : 1);
-    t.min_j_per_lane = 64;
+    t.target_lanes = c->n_cu * t.wg_per_cu * kWG;
+    t.min_j_per_lane = 4;
     return t;
 }
 
@@ -190,9 +191,9 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     CHECK(ensure(c, c->act_cnt, sizeof(int32_t) * C));
     CHECK(ensure(c, c->chunks, sizeof(int32_t) * C));
     CHECK(ensure(c, c->item_off, sizeof(int32_t) * (C + 1)));
-    const int64_t cap = (int64_t)7 * 16 * std::max<int64_t>(n_act_max, 1024);
+    const int64_t cap = (int64_t)7 * 32 * std::max<int64_t>(n_act_max, 4096);
     CHECK(ensure(c, c->partial, sizeof(double) * cap));
-    CHECK(ensure(c, c->counters, sizeof(int64_t) * 8));
+    CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
     std::memset(a, 0, sizeof *a);
     a->xp = xp;
     a->vp = vp;
@@ -239,11 +240,16 @@ int ensure_step_scratch(hermite_ctx* c, int64_t n)
     const int nb = select_blocks(n);
     CHECK(ensure(c, c->sel_min, sizeof(int64_t) * nb));
     CHECK(ensure(c, c->sel_cnt, sizeof(int32_t) * nb));
-    CHECK(ensure(c, c->counters, sizeof(int64_t) * 8));
+    CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
+    if (!c->ticket.p) {
+        CHECK(ensure(c, c->ticket, sizeof(uint32_t) * 4));
+        HIP_OK(hipMemset(c->ticket.p, 0, sizeof(uint32_t) * 4));
+    }
     return HERMITE_OK;
 }
 
-// One block step on stream st using the context's step scratch.
+// One block step on stream st using the context's step scratch: fused
+// select + predict + plan, the persistent sweep, fused reduce + correct.
 int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                  double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
                  hipStream_t st)
@@ -254,15 +260,17 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     int64_t* T = (int64_t*)c->step_T.p;
     double* out = (double*)c->step_out.p;
     int64_t* counters = (int64_t*)c->counters.p;
-    HIP_OK(launch_select(n, s->t, s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
-                         (int32_t*)c->sel_cnt.p, counters, st));
-    HIP_OK(launch_predict(n, s->tick_bits, s->x, s->v, s->a, s->j, s->t, T, 0, na,
-                          s->xp, s->vp, st));
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[precision];
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, na, (int32_t)n, eps2, tu, out,
                         out + 3 * n, out + 6 * n, &a));
-    CHECK(run_force(c, a, precision, tu, false, st));
+    a.ipl = (tu.variant & 1) ? 2 : 1;
+    HIP_OK(launch_step_select(n, s->tick_bits, s->x, s->v, s->a, s->j, s->xp, s->vp, s->t,
+                              s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
+                              (int32_t*)c->sel_cnt.p, counters, (uint32_t*)c->ticket.p, a,
+                              st));
+    HIP_OK(launch_sweep_only(a, precision, tu.variant, std::max(1, c->n_cu * tu.wg_per_cu),
+                             st));
     CorrectArgs ca;
     std::memset(&ca, 0, sizeof ca);
     ca.n = n;
@@ -273,9 +281,6 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.T_dev = T;
     ca.xp = s->xp;
     ca.vp = s->vp;
-    ca.acc1 = out;
-    ca.jrk1 = out + 3 * n;
-    ca.pot1 = out + 6 * n;
     ca.x = s->x;
     ca.v = s->v;
     ca.a = s->a;
@@ -288,7 +293,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.k_min = p->k_min;
     ca.k_max = p->k_max;
     ca.counters = counters;
-    HIP_OK(launch_correct(ca, st));
+    HIP_OK(launch_correct_reduce(ca, a, st));
     return HERMITE_OK;
 }
 
@@ -346,8 +351,8 @@ int hermite_create(int device, hermite_ctx** out)
         return fail(HERMITE_EHIP, "hipStreamCreateWithFlags failed");
     }
     for (int p = 0; p < 3; ++p) c->tuning[p] = default_tuning(c, p);
-    int rc = ensure(c, c->counters, sizeof(int64_t) * 8);
-    if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * 8) != hipSuccess)
+    int rc = ensure(c, c->counters, sizeof(int64_t) * kCounters);
+    if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * kCounters) != hipSuccess)
         rc = fail(HERMITE_EHIP, "hipMemset of counters failed");
     if (rc != HERMITE_OK) {
         hermite_destroy(c);
@@ -365,7 +370,7 @@ int hermite_destroy(hermite_ctx* c)
     drop_graphs(c);
     Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
                    &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
-                   &c->step_T, &c->step_out, &c->phi, &c->counters};
+                   &c->step_T, &c->step_out, &c->phi, &c->counters, &c->ticket};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -591,18 +596,30 @@ int hermite_counters(hermite_ctx* c, int64_t out[5], void* stream)
 {
     CHECK(check_ctx(c));
     if (!out) return fail(HERMITE_EINVAL, "null output pointer");
-    int64_t h[8];
-    HIP_OK(hipMemcpyAsync(h, c->counters.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost,
-                          (hipStream_t)stream));
+    int64_t h[kCounters];
+    HIP_OK(hipMemcpyAsync(h, c->counters.p, sizeof(int64_t) * kCounters,
+                          hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     for (int k = 0; k < 5; ++k) out[k] = h[k];
     return HERMITE_OK;
 }
 
+int hermite_block_histogram(hermite_ctx* c, int64_t out[33], void* stream)
+{
+    CHECK(check_ctx(c));
+    if (!out) return fail(HERMITE_EINVAL, "null output pointer");
+    int64_t h[kCounters];
+    HIP_OK(hipMemcpyAsync(h, c->counters.p, sizeof(int64_t) * kCounters,
+                          hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    for (int k = 0; k < 33; ++k) out[k] = h[kHistBase + k];
+    return HERMITE_OK;
+}
+
 int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                 double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
-                int use_graph, int32_t sync_every, int64_t* steps_out,
-                int64_t* interactions_out, void* stream)
+                int use_graph, int32_t sync_every, int64_t max_steps, int64_t* steps_out,
+                int64_t* interactions_out, int32_t* done_out, void* stream)
 {
     CHECK(check_ctx(c));
     CHECK(check_state(s));
@@ -614,19 +631,29 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
     hipStream_t st = (hipStream_t)stream;
     int64_t c0[5], c1[5];
     CHECK(hermite_counters(c, c0, stream));
+    int64_t launched = 0;
+    int32_t done = 0;
     for (;;) {
-        for (int k = 0; k < sync_every; ++k)
+        int batch = sync_every;
+        if (max_steps > 0 && launched + batch > max_steps) batch = (int)(max_steps - launched);
+        for (int k = 0; k < batch; ++k)
             CHECK(hermite_step(c, s, cl, eps2, precision, p, T_end, use_graph, stream));
+        launched += batch;
         int64_t T = 0;
         int32_t na = 0;
         HIP_OK(hipMemcpyAsync(&T, c->step_T.p, sizeof T, hipMemcpyDeviceToHost, st));
         HIP_OK(hipMemcpyAsync(&na, c->step_na.p, sizeof na, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
-        if (na == 0 || T >= T_end) break;
+        if (na == 0 || T >= T_end) {
+            done = 1;
+            break;
+        }
+        if (max_steps > 0 && launched >= max_steps) break;
     }
     CHECK(hermite_counters(c, c1, stream));
     if (steps_out) *steps_out = c1[0] - c0[0];
     if (interactions_out) *interactions_out = c1[1] - c0[1];
+    if (done_out) *done_out = done;
     return HERMITE_OK;
 }
 
@@ -746,13 +773,15 @@ double max_rel_diff(const std::vector<double>& a, const std::vector<double>& b, 
 
 extern "C" {
 
-int hermite_autotune(hermite_ctx* c, const hermite_state* s, double eps2, int precision,
-                     int32_t n_act, const char* cache_path, void* stream)
+int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                     double eps2, int precision, int32_t n_act, const char* cache_path,
+                     void* stream)
 {
     CHECK(check_ctx(c));
     CHECK(check_state(s));
     CHECK(check_precision(precision));
-    CHECK(check_eps2(eps2));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
     if (n_act < 1 || n_act > s->n) return fail(HERMITE_EINVAL, "n_act out of range [1, n]");
     hipStream_t st = (hipStream_t)stream;
     CHECK(ensure(c, c->step_idx, sizeof(int32_t) * s->n));
@@ -768,7 +797,7 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, double eps2, int pr
     auto run_p = [&](int prec, const hermite_tuning& tu, int reps, double* us,
                      std::vector<double>* res) -> int {
         SweepArgs a;
-        CHECK(prepare_sweep(c, s, nullptr, s->xp, s->vp, idx, nullptr, n_act, eps2, tu, out,
+        CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, nullptr, n_act, eps2, tu, out,
                             out + 3 * (size_t)n_act, out + 6 * (size_t)n_act, &a));
         a.counters = nullptr;
         CHECK(run_force(c, a, prec, tu, false, st));   // warm-up
@@ -812,12 +841,12 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, double eps2, int pr
         double e[3];
         errs(ref, ref64, e);
         for (int q = 0; q < 3; ++q) limit[q] = std::max(tol, 1.5 * e[q]);
-        const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{64}
-                                                   : std::vector<int>{16, 32, 64, 128};
+        const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{4}
+                                                   : std::vector<int>{4, 16, 64};
         const int nvar = precision == HERMITE_FP64 ? 2 : 4;
         for (int var = 0; var < nvar && rc == HERMITE_OK; ++var) {
             for (int w = 2; w <= 8 && rc == HERMITE_OK; ++w) {
-                for (int f : {1, 2, 4}) {
+                for (int f : {1, 2, 4, 8}) {
                     for (int mj : mjs) {
                         hermite_tuning tu;
                         tu.wg_per_cu = w;

@@ -3,6 +3,7 @@
 // All are memory/latency bound; every thread handles whole particles and
 // reads/writes SoA arrays with unit stride.
 #include "hermite_internal.h"
+#include "plan.h"
 
 namespace hm {
 namespace {
@@ -84,19 +85,100 @@ __global__ void __launch_bounds__(kWG) sel_count_kernel(int64_t n, const int64_t
     }
 }
 
-// Stage 3: each block's output offset is the sum of the counts before it;
-// a block-wide scan places every active index in ascending order.
-__global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t* t,
-                                                        const int64_t* dt,
-                                                        const int32_t* block_cnt,
-                                                        int nb, const int64_t* T_in,
-                                                        int64_t T_end, int32_t* idx,
-                                                        int32_t* n_act,
-                                                        int64_t* counters)
+// Stages 1 and 2 in one launch (block-step path): every block finds its
+// minimum of t_i + dt_i and how many of its particles attain it; the last
+// block to finish (atomic ticket) takes the global minimum T and keeps the
+// counts of the blocks whose minimum is T.
+__global__ void __launch_bounds__(kWG) sel_min_count_kernel(int64_t n, const int64_t* t,
+                                                            const int64_t* dt,
+                                                            int64_t* block_min,
+                                                            int32_t* block_cnt, int nb,
+                                                            int64_t* T_out, uint32_t* ticket)
 {
-    __shared__ int32_t sh[kWG];
-    const int64_t T = *T_in;
-    // offset of this block
+    __shared__ int64_t sh[kWG];
+    __shared__ int32_t shc[kWG];
+    __shared__ int32_t s_last;
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock;
+    int64_t e[kSelPer];
+    int64_t v = INT64_MAX;
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
+        e[r] = i < n ? t[i] + dt[i] : INT64_MAX;
+        v = e[r] < v ? e[r] : v;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const int64_t o = sh[threadIdx.x + s];
+            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    const int64_t bmin = sh[0];
+    int32_t c = 0;
+    for (int r = 0; r < kSelPer; ++r) c += (e[r] == bmin) ? 1 : 0;
+    shc[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        block_min[blockIdx.x] = bmin;
+        block_cnt[blockIdx.x] = shc[0];
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(ticket, 1u) == (uint32_t)(nb - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const int64_t T = block_min_all(block_min, nb, sh);
+    for (int b = threadIdx.x; b < nb; b += kWG)
+        if (block_min[b] != T) block_cnt[b] = 0;
+    if (threadIdx.x == 0) {
+        *T_out = T;
+        *ticket = 0u;
+    }
+}
+
+// Stage 3: each block's output offset is the sum of the counts before it;
+// a block-wide scan places every active index in ascending order.  The
+// block-step path also predicts the block's particles here (T is known),
+// and the last block to finish (atomic ticket) totals n_act, updates the
+// counters and builds the sweep plan, so that one launch does the work of
+// three.
+struct PredictArgs {
+    double tick;
+    const double* x;
+    const double* v;
+    const double* a;
+    const double* j;
+    double* xp;
+    double* vp;
+};
+
+__device__ __forceinline__ void predict_one(int64_t n, int64_t i, int64_t T, const int64_t* t,
+                                            const PredictArgs& pa)
+{
+    const double h = (double)(T - t[i]) * pa.tick;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = d * n + i;
+        const double a2 = pa.a[o] * 0.5;
+        const double j6 = pa.j[o] * (1.0 / 6.0);
+        const double j2 = pa.j[o] * 0.5;
+        pa.xp[o] = fma(h, fma(h, fma(h, j6, a2), pa.v[o]), pa.x[o]);
+        pa.vp[o] = fma(h, fma(h, j2, pa.a[o]), pa.v[o]);
+    }
+}
+
+// Writes this block's active indices; returns the block's active count.
+__device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt,
+                                  const int32_t* block_cnt, int64_t T, bool live,
+                                  int32_t* idx, int32_t* sh)
+{
     int32_t pre = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += kWG) pre += block_cnt[b];
     sh[threadIdx.x] = pre;
@@ -126,49 +208,95 @@ __global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t
         __syncthreads();
     }
     int32_t pos = off + sh[threadIdx.x] - c;
-    const bool live = T <= T_end;
+    const int32_t block_total = sh[kWG - 1];
     if (live) {
         for (int r = 0; r < kSelPer; ++r)
             if (f[r]) idx[pos++] = (int32_t)(base + r);
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == kWG - 1) {
-        const int32_t total = off + sh[kWG - 1];
-        const int32_t na = live ? total : 0;
-        *n_act = na;
-        if (counters) {
-            counters[0] += na > 0 ? 1 : 0;
-            counters[3] = T;
-            counters[4] = na;
-        }
+    __syncthreads();
+    return off + block_total;
+}
+
+__device__ void count_step(int64_t* counters, int64_t T, int32_t na)
+{
+    if (counters) {
+        counters[0] += na > 0 ? 1 : 0;
+        counters[3] = T;
+        counters[4] = na;
+        const int bin = na > 0 ? 32 - __clz(na) : 0;   // block-size histogram
+        counters[kHistBase + bin] += 1;
     }
 }
 
+__global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t* t,
+                                                        const int64_t* dt,
+                                                        const int32_t* block_cnt,
+                                                        int nb, const int64_t* T_in,
+                                                        int64_t T_end, int32_t* idx,
+                                                        int32_t* n_act,
+                                                        int64_t* counters)
+{
+    __shared__ int32_t sh[kWG];
+    const int64_t T = *T_in;
+    const bool live = T <= T_end;
+    const int32_t upto = sel_write_body(n, t, dt, block_cnt, T, live, idx, sh);
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+        const int32_t na = live ? upto : 0;
+        *n_act = na;
+        count_step(counters, T, na);
+    }
+}
+
+__global__ void __launch_bounds__(kWG) sel_write_predict_plan_kernel(
+    int64_t n, const int64_t* t, const int64_t* dt, const int32_t* block_cnt, int nb,
+    const int64_t* T_in, int64_t T_end, int32_t* idx, int32_t* n_act, int64_t* counters,
+    PredictArgs pa, SweepArgs sa, uint32_t* ticket)
+{
+    __shared__ int32_t sh[kWG];
+    __shared__ int32_t s_last;
+    const int64_t T = *T_in;
+    const bool live = T <= T_end;
+    const int32_t upto = sel_write_body(n, t, dt, block_cnt, T, live, idx, sh);
+    if (live) {
+        const int64_t base = (int64_t)blockIdx.x * kSelBlock;
+        for (int r = 0; r < kSelPer; ++r) {
+            const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
+            if (i < n) predict_one(n, i, T, t, pa);
+        }
+    }
+    // the last block to arrive sees every block's indices
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(ticket, 1u) == (uint32_t)(nb - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    __shared__ int32_t s_na;
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int b = 0; b < nb; ++b) tot += block_cnt[b];
+        const int32_t na = live ? tot : 0;
+        (void)upto;
+        *n_act = na;
+        count_step(counters, T, na);
+        *ticket = 0u;
+        s_na = na;
+    }
+    __syncthreads();
+    plan_body(sa, s_na);
+}
+
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
-__global__ void __launch_bounds__(kWG) predict_kernel(int64_t n, double tick,
-                                                      const double* __restrict__ x,
-                                                      const double* __restrict__ v,
-                                                      const double* __restrict__ a,
-                                                      const double* __restrict__ j,
-                                                      const int64_t* __restrict__ t,
+__global__ void __launch_bounds__(kWG) predict_kernel(int64_t n, const int64_t* __restrict__ t,
                                                       const int64_t* T_dev, int64_t T_host,
                                                       const int32_t* n_act_dev,
-                                                      double* __restrict__ xp,
-                                                      double* __restrict__ vp)
+                                                      PredictArgs pa)
 {
     if (n_act_dev && *n_act_dev == 0) return;
     const int64_t T = T_dev ? *T_dev : T_host;
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (i >= n) return;
-    const double h = (double)(T - t[i]) * tick;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int64_t o = d * n + i;
-        const double a2 = a[o] * 0.5;
-        const double j6 = j[o] * (1.0 / 6.0);
-        const double j2 = j[o] * 0.5;
-        xp[o] = fma(h, fma(h, fma(h, j6, a2), v[o]), x[o]);
-        vp[o] = fma(h, fma(h, j2, a[o]), v[o]);
-    }
+    predict_one(n, i, T, t, pa);
 }
 
 // ---- timestep: Aarseth criterion and power-of-two quantisation ----------
@@ -205,25 +333,22 @@ __device__ __forceinline__ int log2_ticks(int64_t dt)
 }
 
 // ---- corrector + next step (procedure steps 5-8) -------------------------
-__global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
+// a1, j1: the new acceleration and jerk of active position p.
+__device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double a1v[3],
+                            const double j1v[3], double pot1, bool have_pot)
 {
-    const int na = c.n_act_dev ? *c.n_act_dev : c.n_act_max;
-    const int p = blockIdx.x * kWG + threadIdx.x;
-    if (p >= na) return;
-    const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     const int64_t n = c.n;
-    const int64_t st = c.n_act_max;
     const int i = c.idx ? c.idx[p] : p;
     const double tick = ldexp(1.0, -c.tick_bits);
     const int64_t dt_old = c.dt[i];
     const double h = (double)dt_old * tick;
     const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
-    double s1[3], cc[3], a1v[3], j1v[3];
+    double s1[3], cc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int64_t o = d * n + i;
         const double a0 = c.a[o], j0 = c.j[o];
-        const double a1 = c.acc1[d * st + p], j1 = c.jrk1[d * st + p];
+        const double a1 = a1v[d], j1 = j1v[d];
         const double da = a0 - a1;
         const double s0 = 2.0 * (-3.0 * da - (2.0 * j0 + j1) * h) / h2;
         const double c0 = 6.0 * (2.0 * da + (j0 + j1) * h) / h3;
@@ -233,10 +358,8 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
         c.j[o] = j1;
         s1[d] = fma(c0, h, s0);
         cc[d] = c0;
-        a1v[d] = a1;
-        j1v[d] = j1;
     }
-    if (c.pot1) c.pot[i] = c.pot1[p];
+    if (have_pot) c.pot[i] = pot1;
     c.t[i] = T;
     const double A = norm3(a1v[0], a1v[1], a1v[2]);
     const double J = norm3(j1v[0], j1v[1], j1v[2]);
@@ -249,6 +372,52 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
     int cl;
     c.dt[i] = quantize_dt(crit, k_old, T, c.tick_bits, c.k_min, c.k_max, &cl);
     if (cl && c.counters) atomicAdd((unsigned long long*)&c.counters[2], 1ull);
+}
+
+__global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
+{
+    const int na = c.n_act_dev ? *c.n_act_dev : c.n_act_max;
+    const int p = blockIdx.x * kWG + threadIdx.x;
+    if (p >= na) return;
+    const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
+    const int64_t st = c.n_act_max;
+    double a1[3], j1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a1[d] = c.acc1[d * st + p];
+        j1[d] = c.jrk1[d * st + p];
+    }
+    correct_one(c, p, T, a1, j1, c.pot1 ? c.pot1[p] : 0.0, c.pot1 != nullptr);
+}
+
+// The block-step corrector: sums the sweep's j-chunk partials of position p
+// in fixed order (the reduce stage) and corrects in the same kernel.
+// Grid-stride: a thread per particle for few chunks, a wave for many.
+__global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, SweepArgs sa)
+{
+    const int na = sa.plan->n_act;
+    const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
+    if (sa.plan->s_max <= kWaveReduceChunks) {
+        for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
+            double s[7];
+            reduce_partials(sa, na, p, s);
+            const double a1[3] = {s[0], s[1], s[2]};
+            const double j1[3] = {s[3], s[4], s[5]};
+            correct_one(c, p, T, a1, j1, s[6], true);
+        }
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int wpb = kWG / 64;
+        for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
+            double s[7];
+            reduce_partials_wave(sa, na, p, lane, s);
+            if (lane == 0) {
+                const double a1[3] = {s[0], s[1], s[2]};
+                const double j1[3] = {s[3], s[4], s[5]};
+                correct_one(c, p, T, a1, j1, s[6], true);
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kWG) init_dt_kernel(int64_t n, int tick_bits,
@@ -348,9 +517,33 @@ hipError_t launch_predict(int64_t n, int tick_bits, const double* x,
                           int64_t T_host, const int32_t* n_act_dev,
                           double* xp, double* vp, hipStream_t st)
 {
-    const double tick = ldexp(1.0, -tick_bits);
-    hipLaunchKernelGGL(predict_kernel, dim3(nblocks(n, kWG)), dim3(kWG), 0, st, n,
-                       tick, x, v, a, j, t, T_dev, T_host, n_act_dev, xp, vp);
+    PredictArgs pa{ldexp(1.0, -tick_bits), x, v, a, j, xp, vp};
+    hipLaunchKernelGGL(predict_kernel, dim3(nblocks(n, kWG)), dim3(kWG), 0, st, n, t, T_dev,
+                       T_host, n_act_dev, pa);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_select(int64_t n, int tick_bits, const double* x, const double* v,
+                              const double* a, const double* j, double* xp, double* vp,
+                              const int64_t* t, const int64_t* dt, int64_t T_end,
+                              int32_t* idx, int32_t* n_act, int64_t* T, int64_t* block_min,
+                              int32_t* block_cnt, int64_t* counters, uint32_t* ticket,
+                              const SweepArgs& sa, hipStream_t st)
+{
+    const int nb = nblocks(n, kSelBlock);
+    PredictArgs pa{ldexp(1.0, -tick_bits), x, v, a, j, xp, vp};
+    hipLaunchKernelGGL(sel_min_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min,
+                       block_cnt, nb, T, ticket + 1);
+    hipLaunchKernelGGL(sel_write_predict_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                       (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
+                       counters, pa, sa, ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st)
+{
+    hipLaunchKernelGGL(correct_reduce_kernel, dim3(reduce_grid(c.n_act_max)), dim3(kWG), 0,
+                       st, c, sa);
     return hipGetLastError();
 }
 

@@ -1,0 +1,198 @@
+// Device-side planning of a force sweep, shared by the standalone plan
+// kernel and the fused block-step selection kernel, plus the fixed-order
+// reduction of j-chunk partial sums.
+#pragma once
+
+#include "hermite_internal.h"
+
+namespace hm {
+
+template <typename T>
+__device__ inline int upper_bound_i64(const int64_t* a, int count, T key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= (int64_t)key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int upper_bound_i32(const int32_t* a, int count, int key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int lower_bound_idx(const int32_t* a, int count, int64_t key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------
+// Plan: one workgroup (all kWG threads must call this) turns the active
+// count into a split (lanes per particle L, chunk length jc) and a work
+// list of (cluster, i-tile, j-chunk) items, and adds the sweep's
+// interaction count to the counters.
+// ------------------------------------------------------------------------
+__device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
+{
+    __shared__ int32_t s_items[kWG];
+    __shared__ int32_t s_cmax[kWG];
+    __shared__ int64_t s_inter[kWG];
+    __shared__ int32_t s_na, s_L, s_ti;
+    __shared__ int64_t s_jc;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
+        // Work items wanted (about one per resident workgroup slot, times
+        // the tuning factor), and the most j-chunks a cluster can give
+        // (each chunk at least one LDS tile).
+        const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
+        // j-chunks available per active particle: each chunk at least one
+        // LDS tile, and all partial sums must fit the scratch buffer.
+        int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
+        if (na > 0) {
+            const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
+            if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
+        }
+        // Fewest lanes per particle that still yields enough items: more
+        // particles per item means more work per staged j tile.
+        int32_t L = 1;
+        for (; L < 64; L <<= 1) {
+            const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+            const int64_t tiles = (na + ti_l - 1) / ti_l;
+            if (tiles * s_cap >= want) break;
+        }
+        const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+        const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l : 1;
+        int64_t S = (want + tiles - 1) / tiles;
+        if (S > s_cap) S = s_cap;
+        if (S < 1) S = 1;
+        int64_t jc = (a.n_cmax + S - 1) / S;
+        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
+        if (jc < jmin) jc = jmin;
+        jc = (jc + kTJ - 1) / kTJ * kTJ;
+        // rounding jc up can only lower the chunk count, so the buffer fits
+        s_na = na; s_L = L; s_ti = a.ipl * (kWG / L); s_jc = jc;
+    }
+    __syncthreads();
+    const int32_t na = s_na, ti = s_ti;
+    const int64_t jc = s_jc;
+    const int C = a.n_clusters;
+    const int per = (C + kWG - 1) / kWG;
+    const int c0 = tid * per;
+    const int c1 = (c0 + per < C) ? c0 + per : C;
+    int32_t local = 0, cmax = 0;
+    int64_t inter = 0;
+    for (int c = c0; c < c1; ++c) {
+        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
+        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
+        int32_t st, cnt;
+        if (C == 1) {
+            st = 0; cnt = na;
+        } else if (a.idx == nullptr) {
+            const int64_t e = o1 < na ? o1 : na;
+            st = (int32_t)o0;
+            cnt = e > o0 ? (int32_t)(e - o0) : 0;
+        } else {
+            st = lower_bound_idx(a.idx, na, o0);
+            cnt = lower_bound_idx(a.idx, na, o1) - st;
+        }
+        const int32_t tiles = (cnt + ti - 1) / ti;
+        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
+        a.act_start[c] = st;
+        a.act_cnt[c] = cnt;
+        a.chunks[c] = ch;
+        local += tiles * ch;
+        cmax = ch > cmax ? ch : cmax;
+        inter += (int64_t)cnt * (o1 - o0);
+    }
+    s_items[tid] = local;
+    s_cmax[tid] = cmax;
+    s_inter[tid] = inter;
+    __syncthreads();
+    // inclusive scan of item counts (Hillis-Steele), max and sum
+    for (int d = 1; d < kWG; d <<= 1) {
+        int32_t v = tid >= d ? s_items[tid - d] : 0;
+        int32_t mx = tid >= d ? s_cmax[tid - d] : 0;
+        int64_t iv = tid >= d ? s_inter[tid - d] : 0;
+        __syncthreads();
+        s_items[tid] += v;
+        s_cmax[tid] = mx > s_cmax[tid] ? mx : s_cmax[tid];
+        s_inter[tid] += iv;
+        __syncthreads();
+    }
+    int32_t base = tid > 0 ? s_items[tid - 1] : 0;
+    for (int c = c0; c < c1; ++c) {
+        a.item_off[c] = base;
+        base += ((a.act_cnt[c] + ti - 1) / ti) * a.chunks[c];
+    }
+    if (tid == kWG - 1) {
+        a.item_off[C] = s_items[kWG - 1];
+        SweepPlan* P = a.plan;
+        P->n_act = na;
+        P->L = s_L;
+        P->ti = ti;
+        P->s_max = s_cmax[kWG - 1];
+        P->jc = jc;
+        P->total_items = s_items[kWG - 1];
+        P->next_item = 0u;
+        if (a.counters) {
+            a.counters[1] += s_inter[kWG - 1];
+        }
+    }
+}
+
+
+__device__ inline int cluster_of(const SweepArgs& a, int p)
+{
+    if (a.n_clusters <= 1) return 0;
+    const int i = a.idx ? a.idx[p] : p;
+    return upper_bound_i64(a.offsets, a.n_clusters + 1, i) - 1;
+}
+
+// Sum, in chunk order, of the partial results of active position p:
+// out = acc xyz, jerk xyz, pot.  One thread per particle.
+__device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[7])
+{
+    const int ch = a.chunks[cluster_of(a, p)];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) out[q] = 0.0;
+    for (int k = 0; k < ch; ++k) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) out[q] += a.partial[((int64_t)k * 7 + q) * na + p];
+    }
+}
+
+// The same sum by a whole wave (for many chunks): lane l adds chunks
+// l, l + 64, ... in order, then a fixed xor butterfly combines the lanes.
+// Every lane returns the total.  Deterministic for a given chunk count.
+__device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, int lane,
+                                            double out[7])
+{
+    const int ch = a.chunks[cluster_of(a, p)];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) out[q] = 0.0;
+    for (int k = lane; k < ch; k += 64) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) out[q] += a.partial[((int64_t)k * 7 + q) * na + p];
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+        for (int o = 1; o < 64; o <<= 1) out[q] += __shfl_xor(out[q], o);
+}
+
+// Chunk counts above this use the wave-per-particle reduction.
+constexpr int kWaveReduceChunks = 16;
+
+}  // namespace hm

@@ -34,6 +34,7 @@
 //  MIXED_2F as MIXED, with the running sums held as two FP32 words
 //           (hi + lo) updated by Knuth's TwoSum.
 #include "hermite_internal.h"
+#include "plan.h"
 
 #include <type_traits>
 
@@ -53,138 +54,9 @@ __device__ __forceinline__ double rsqrt_f64(double s)
     return fma(y * e, p, y);
 }
 
-template <typename T>
-__device__ __forceinline__ int upper_bound_i64(const int64_t* a, int count, T key)
-{
-    int lo = 0, hi = count;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] <= (int64_t)key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int upper_bound_i32(const int32_t* a, int count, int key)
-{
-    int lo = 0, hi = count;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] <= key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int lower_bound_idx(const int32_t* a, int count, int64_t key)
-{
-    int lo = 0, hi = count;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int64_t)a[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// ------------------------------------------------------------------------
-// Plan: one workgroup turns the device-resident active count into a split
-// (lanes per particle L, chunk length jc) and a work list.
-// ------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWG) plan_kernel(SweepArgs a)
 {
-    __shared__ int32_t s_items[kWG];
-    __shared__ int32_t s_cmax[kWG];
-    __shared__ int64_t s_inter[kWG];
-    __shared__ int32_t s_na, s_L, s_ti;
-    __shared__ int64_t s_jc;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        int32_t na = a.n_act_dev ? *a.n_act_dev : a.n_act_max;
-        na = na < 0 ? 0 : (na > a.n_act_max ? a.n_act_max : na);
-        const int32_t nl = (na + a.ipl - 1) / a.ipl;   // lanes' worth of particles
-        int32_t L = 1;
-        while (L < 64 && (int64_t)nl * L * 2 <= (int64_t)a.target_lanes) L <<= 1;
-        const int64_t lanes = (int64_t)(nl > 0 ? nl : 1) * L;
-        int64_t S = (int64_t)a.target_lanes / lanes;
-        if (S < 1) S = 1;
-        int64_t jc = (a.n_cmax + S - 1) / S;
-        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
-        if (jc < jmin) jc = jmin;
-        jc = (jc + kTJ - 1) / kTJ * kTJ;
-        if (na > 0) {
-            const int64_t smax_cap = a.partial_cap / (7 * (int64_t)na);
-            const int64_t smax = (a.n_cmax + jc - 1) / jc;
-            if (smax > smax_cap) {
-                jc = (a.n_cmax + smax_cap - 1) / smax_cap;
-                jc = (jc + kTJ - 1) / kTJ * kTJ;
-            }
-        }
-        s_na = na; s_L = L; s_ti = a.ipl * (kWG / L); s_jc = jc;
-    }
-    __syncthreads();
-    const int32_t na = s_na, ti = s_ti;
-    const int64_t jc = s_jc;
-    const int C = a.n_clusters;
-    const int per = (C + kWG - 1) / kWG;
-    const int c0 = tid * per;
-    const int c1 = (c0 + per < C) ? c0 + per : C;
-    int32_t local = 0, cmax = 0;
-    int64_t inter = 0;
-    for (int c = c0; c < c1; ++c) {
-        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
-        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
-        int32_t st, cnt;
-        if (C == 1) {
-            st = 0; cnt = na;
-        } else if (a.idx == nullptr) {
-            const int64_t e = o1 < na ? o1 : na;
-            st = (int32_t)o0;
-            cnt = e > o0 ? (int32_t)(e - o0) : 0;
-        } else {
-            st = lower_bound_idx(a.idx, na, o0);
-            cnt = lower_bound_idx(a.idx, na, o1) - st;
-        }
-        const int32_t tiles = (cnt + ti - 1) / ti;
-        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
-        a.act_start[c] = st;
-        a.act_cnt[c] = cnt;
-        a.chunks[c] = ch;
-        local += tiles * ch;
-        cmax = ch > cmax ? ch : cmax;
-        inter += (int64_t)cnt * (o1 - o0);
-    }
-    s_items[tid] = local;
-    s_cmax[tid] = cmax;
-    s_inter[tid] = inter;
-    __syncthreads();
-    // inclusive scan of item counts (Hillis-Steele), max and sum
-    for (int d = 1; d < kWG; d <<= 1) {
-        int32_t v = tid >= d ? s_items[tid - d] : 0;
-        int32_t mx = tid >= d ? s_cmax[tid - d] : 0;
-        int64_t iv = tid >= d ? s_inter[tid - d] : 0;
-        __syncthreads();
-        s_items[tid] += v;
-        s_cmax[tid] = mx > s_cmax[tid] ? mx : s_cmax[tid];
-        s_inter[tid] += iv;
-        __syncthreads();
-    }
-    int32_t base = tid > 0 ? s_items[tid - 1] : 0;
-    for (int c = c0; c < c1; ++c) {
-        a.item_off[c] = base;
-        base += ((a.act_cnt[c] + ti - 1) / ti) * a.chunks[c];
-    }
-    if (tid == kWG - 1) {
-        a.item_off[C] = s_items[kWG - 1];
-        SweepPlan* P = a.plan;
-        P->n_act = na;
-        P->L = s_L;
-        P->ti = ti;
-        P->s_max = s_cmax[kWG - 1];
-        P->jc = jc;
-        P->total_items = s_items[kWG - 1];
-        P->next_item = 0u;
-        if (a.counters) {
-            a.counters[1] += s_inter[kWG - 1];
-        }
-    }
+    plan_body(a, a.n_act_dev ? *a.n_act_dev : a.n_act_max);
 }
 
 // ------------------------------------------------------------------------
@@ -495,6 +367,47 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[7])
     out[6] = -S.pp.value();
 }
 
+// Direct mode, used when a whole wave shares each active particle
+// (L = 64, tiny active blocks): lane l takes j = j0 + l, j0 + l + 64, ...
+// straight from global memory (coalesced, L2-resident), so there is no LDS
+// staging and no barrier in the loop; only latency matters in this regime.
+template <int PREC, int IPL, typename RUN>
+__device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int64_t j1,
+                                            int lane, const int (&ii)[IPL],
+                                            const I64 (&I)[IPL], double eps2,
+                                            SumF (&F)[IPL], RUN (&S)[IPL])
+{
+    const int64_t n = a.n;
+    const float eps2f = (float)eps2;
+    int run = 0;
+    for (int64_t jj = j0 + lane; jj < j1; jj += 64) {
+        const double xj = a.xp[jj], yj = a.xp[n + jj], zj = a.xp[2 * n + jj];
+        const double vxj = a.vp[jj], vyj = a.vp[n + jj], vzj = a.vp[2 * n + jj];
+        const double mj = a.m[jj];
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const bool self = jj == (int64_t)ii[q];
+            if constexpr (PREC == 0) {
+                pair_f64<true>(I[q], eps2, xj, yj, zj, vxj, vyj, vzj, mj, self, S[q]);
+            } else {
+                pair_mixed<true>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, (float)mj, self,
+                                 F[q]);
+            }
+        }
+        if constexpr (PREC != 0) {
+            if (++run == kMixedK) {
+                run = 0;
+#pragma unroll
+                for (int q = 0; q < IPL; ++q) flush(F[q], S[q]);
+            }
+        }
+    }
+    if constexpr (PREC != 0) {
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) flush(F[q], S[q]);
+    }
+}
+
 // ------------------------------------------------------------------------
 // The persistent sweep kernel.
 //   PREC 0 = FP64, 1 = mixed (FP64 running sums), 2 = mixed two-float.
@@ -526,11 +439,10 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     const int C = a.n_clusters;
     const int64_t n = a.n;
 
-    for (;;) {
-        if (tid == 0) s_item = (int32_t)atomicAdd(&P->next_item, 1u);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
+    // Workgroup w starts with item w; only when there are more items than
+    // workgroups do the finished ones take further items from the counter.
+    int item = blockIdx.x;
+    for (;; ) {
         if (item >= total) break;
 
         const int c = (C == 1) ? 0 : upper_bound_i32(a.item_off, C + 1, item) - 1;
@@ -575,7 +487,13 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             F[q].zero();
         }
 
-        for (int64_t tb = j0; tb < j1; tb += kTJ) {
+        if constexpr (!POT_ONLY) {
+            if (L == 64) {
+                // wave-uniform: every lane of the wave serves the same particles
+                direct_loop<PREC, IPL>(a, j0, j1, sub, ii, I, eps2, F, S);
+            }
+        }
+        for (int64_t tb = j0; tb < j1 && (POT_ONLY || L < 64); tb += kTJ) {
             const int cnt = (int)((j1 - tb) < kTJ ? (j1 - tb) : kTJ);
             __syncthreads();
             if (tid < cnt) {
@@ -638,35 +556,24 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                 }
             }
         }
+        if (total <= (int)gridDim.x) break;
+        __syncthreads();
+        if (tid == 0) s_item = (int32_t)gridDim.x + (int32_t)atomicAdd(&P->next_item, 1u);
+        __syncthreads();
+        item = s_item;
     }
 }
 
 // Adds the j-chunk partial sums of every active particle in chunk order.
+// Grid-stride over particles: one thread each when chunks are few, one
+// wave each when they are many (the launch shape does not depend on n_act).
 template <bool POT_ONLY>
-__global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
+__device__ __forceinline__ void store_reduced(const SweepArgs& a, int p, const double s[7])
 {
-    const int na = a.plan->n_act;
-    const int p = blockIdx.x * kWG + threadIdx.x;
-    if (p >= na) return;
-    int c = 0;
-    if (a.n_clusters > 1) {
-        const int i = a.idx ? a.idx[p] : p;
-        c = upper_bound_i64(a.offsets, a.n_clusters + 1, i) - 1;
-    }
-    const int ch = a.chunks[c];
     const int64_t st = a.n_act_max;
     if (POT_ONLY) {
-        double s = 0.0;
-        for (int k = 0; k < ch; ++k) s += a.partial[((int64_t)k * 7 + 6) * na + p];
-        a.pot[p] = s;
+        a.pot[p] = s[6];
         return;
-    }
-    double s[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) s[q] = 0.0;
-    for (int k = 0; k < ch; ++k) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) s[q] += a.partial[((int64_t)k * 7 + q) * na + p];
     }
     a.acc[p] = s[0];
     a.acc[st + p] = s[1];
@@ -677,6 +584,27 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
         a.jerk[2 * st + p] = s[5];
     }
     if (a.pot) a.pot[p] = s[6];
+}
+
+template <bool POT_ONLY>
+__global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
+{
+    const int na = a.plan->n_act;
+    if (a.plan->s_max <= kWaveReduceChunks) {
+        for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
+            double s[7];
+            reduce_partials(a, na, p, s);
+            store_reduced<POT_ONLY>(a, p, s);
+        }
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int wpb = kWG / 64;
+        for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
+            double s[7];
+            reduce_partials_wave(a, na, p, lane, s);
+            if (lane == 0) store_reduced<POT_ONLY>(a, p, s);
+        }
+    }
 }
 
 typedef void (*SweepFn)(SweepArgs);
@@ -700,6 +628,15 @@ SweepFn sweep_fn(int precision, int variant, bool pot_only)
 
 }  // namespace
 
+hipError_t launch_sweep_only(const SweepArgs& a_in, int precision, int variant, int grid,
+                             hipStream_t st)
+{
+    SweepArgs a = a_in;
+    a.ipl = (variant & 1) ? 2 : 1;
+    hipLaunchKernelGGL(sweep_fn(precision, variant, false), dim3(grid), dim3(kWG), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_force(const SweepArgs& a_in, int precision, int variant,
                         int grid, bool pot_only, hipStream_t st)
 {
@@ -707,7 +644,7 @@ hipError_t launch_force(const SweepArgs& a_in, int precision, int variant,
     a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
     hipLaunchKernelGGL(sweep_fn(precision, variant, pot_only), dim3(grid), dim3(kWG), 0, st, a);
-    const int rgrid = (a.n_act_max + kWG - 1) / kWG;
+    const int rgrid = reduce_grid(a.n_act_max);
     if (pot_only) {
         hipLaunchKernelGGL(reduce_kernel<true>, dim3(rgrid), dim3(kWG), 0, st, a);
     } else {

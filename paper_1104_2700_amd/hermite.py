@@ -78,12 +78,13 @@ _SIGS = {
     "hermite_initialize": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _P]),
     "hermite_energy": ([_P, _PS, _PC, _d, _P, _P]),
     "hermite_step": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _i64, ctypes.c_int, _P]),
-    "hermite_run": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _i64, ctypes.c_int, _i32,
-                     ctypes.POINTER(_i64), ctypes.POINTER(_i64), _P]),
+    "hermite_run": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _i64, ctypes.c_int, _i32, _i64,
+                     ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32), _P]),
     "hermite_counters": ([_P, ctypes.POINTER(_i64), _P]),
+    "hermite_block_histogram": ([_P, ctypes.POINTER(_i64), _P]),
     "hermite_get_tuning": ([_P, ctypes.c_int, _PT]),
     "hermite_set_tuning": ([_P, ctypes.c_int, _PT]),
-    "hermite_autotune": ([_P, _PS, _d, ctypes.c_int, _i32, ctypes.c_char_p, _P]),
+    "hermite_autotune": ([_P, _PS, _PC, _d, ctypes.c_int, _i32, ctypes.c_char_p, _P]),
     "hermite_load_tuning": ([_P, ctypes.c_char_p, ctypes.c_int, _i64, _i32]),
 }
 for _name, _args in _SIGS.items():
@@ -278,14 +279,26 @@ class Context:
                                 int(bool(use_graph)), _stream(stream)), "hermite_step")
 
     def run(self, s: State, eps2, params, T_end, precision=FP64, use_graph=True,
-            sync_every=64, clusters=None, stream=None):
-        """Integrate to T_end ticks; returns (block steps, interactions)."""
-        steps, inter = _i64(0), _i64(0)
+            sync_every=64, clusters=None, max_steps=0, stream=None, with_done=False):
+        """Integrate to T_end ticks (or max_steps launched steps); returns
+        (block steps, interactions) and, with ``with_done``, whether every
+        particle reached T_end."""
+        steps, inter, done = _i64(0), _i64(0), _i32(0)
         _check(lib.hermite_run(self.h, ctypes.byref(s.c()), _cl(clusters), float(eps2),
                                int(precision), ctypes.byref(params), int(T_end),
-                               int(bool(use_graph)), int(sync_every), ctypes.byref(steps),
-                               ctypes.byref(inter), _stream(stream)), "hermite_run")
+                               int(bool(use_graph)), int(sync_every), int(max_steps),
+                               ctypes.byref(steps), ctypes.byref(inter), ctypes.byref(done),
+                               _stream(stream)), "hermite_run")
+        if with_done:
+            return steps.value, inter.value, bool(done.value)
         return steps.value, inter.value
+
+    def block_histogram(self, stream=None):
+        """Block steps per active-size bin: [0] n_act = 0, [b] 2^(b-1) <= n_act < 2^b."""
+        out = (_i64 * 33)()
+        _check(lib.hermite_block_histogram(self.h, out, _stream(stream)),
+               "hermite_block_histogram")
+        return list(out)
 
     def counters(self, stream=None):
         out = (_i64 * 5)()
@@ -307,11 +320,13 @@ class Context:
                "hermite_set_tuning")
 
     def autotune(self, s: State, eps2, precision=FP64, n_act=None, cache_path=None,
-                 stream=None):
+                 clusters=None, stream=None):
+        """Times launch shapes at s.xp/s.vp and installs the fastest valid one."""
         n_act = s.n if n_act is None else int(n_act)
         path = None if cache_path is None else str(cache_path).encode()
-        _check(lib.hermite_autotune(self.h, ctypes.byref(s.c()), float(eps2), int(precision),
-                                    n_act, path, _stream(stream)), "hermite_autotune")
+        _check(lib.hermite_autotune(self.h, ctypes.byref(s.c()), _cl(clusters), float(eps2),
+                                    int(precision), n_act, path, _stream(stream)),
+               "hermite_autotune")
         return self.get_tuning(precision)
 
     def load_tuning(self, cache_path, precision, n, n_act):
