@@ -34,9 +34,7 @@ def build(force: bool = False) -> str:
             and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
+    compile_source(_SRC, tmp)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -44,30 +42,42 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def configure(lib):
+    """Declares the C signatures on a loaded oracle library; returns it."""
+    d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    P = ctypes.c_void_p
+    lib.oracle_force.argtypes = [i64, P, P, P, i64, P, d, i64, i64, P, P, P, P]
+    lib.oracle_force.restype = None
+    lib.oracle_predict.argtypes = [i64, P, P, P, P, P, i64, i32, P, P]
+    lib.oracle_predict.restype = None
+    lib.oracle_select.argtypes = [i64, P, P, P, P]
+    lib.oracle_select.restype = i64
+    lib.oracle_aarseth.argtypes = [P, P, P, P, d, i32]
+    lib.oracle_aarseth.restype = d
+    lib.oracle_quantize.argtypes = [d, i32, i64, i32, i32, i32, P, P]
+    lib.oracle_quantize.restype = i64
+    lib.oracle_correct.argtypes = ([i64, i64, P, i64, i32] + [P] * 5
+                                   + [P] * 7 + [d, i32, i32, i32, P])
+    lib.oracle_correct.restype = i64
+    lib.oracle_init_dt.argtypes = [i64, P, P, P, P, i32, d, i32, i32, i32]
+    lib.oracle_init_dt.restype = i64
+    lib.oracle_energy.argtypes = [i64, P, P, P, d, P, P, P, P, P, P]
+    lib.oracle_energy.restype = None
+    return lib
+
+
+def compile_source(src_path, out_path):
+    """Compiles an oracle C source with the oracle's flags (strict IEEE)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", out_path, src_path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 def _L():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
-        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
-        P = ctypes.c_void_p
-        lib.oracle_force.argtypes = [i64, P, P, P, i64, P, d, i64, i64, P, P, P, P]
-        lib.oracle_force.restype = None
-        lib.oracle_predict.argtypes = [i64, P, P, P, P, P, i64, i32, P, P]
-        lib.oracle_predict.restype = None
-        lib.oracle_select.argtypes = [i64, P, P, P, P]
-        lib.oracle_select.restype = i64
-        lib.oracle_aarseth.argtypes = [P, P, P, P, d, i32]
-        lib.oracle_aarseth.restype = d
-        lib.oracle_quantize.argtypes = [d, i32, i64, i32, i32, i32, P, P]
-        lib.oracle_quantize.restype = i64
-        lib.oracle_correct.argtypes = ([i64, i64, P, i64, i32] + [P] * 5
-                                       + [P] * 7 + [d, i32, i32, i32, P])
-        lib.oracle_correct.restype = i64
-        lib.oracle_init_dt.argtypes = [i64, P, P, P, P, i32, d, i32, i32, i32]
-        lib.oracle_init_dt.restype = i64
-        lib.oracle_energy.argtypes = [i64, P, P, P, d, P, P, P, P, P, P]
-        lib.oracle_energy.restype = None
-        _lib = lib
+        _lib = configure(ctypes.CDLL(build()))
     return _lib
 
 
