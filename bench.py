@@ -160,6 +160,12 @@ def main():
     r = results[head]
     achieved = FLOPS_ALGO * N * N / (r["sweep_ms"] * 1e-3)
     peak = PEAK_FP32 if head != "fp64" else PEAK_FP64
+    prof = profiled_counters(r["tuning"]["variant"])
+    traffic = issued = None
+    if prof is not None and head in prof:
+        traffic = prof[head]["traffic_bytes"]
+        fl = prof[head]["fp32_flops_per_interaction"] + prof[head]["fp64_flops_per_interaction"]
+        issued = fl * N * N / (r["sweep_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": r["interactions_per_s"],
@@ -187,7 +193,9 @@ def main():
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "issued_tflops_from_counters": issued,
             "flops_per_interaction": FLOPS_ALGO,
             "frac_vs_fp64_or_unpacked_fp32_peak": achieved / PEAK_FP64,
         },
@@ -202,6 +210,26 @@ def main():
             "fp64_sweep_frac_fp64_peak": FLOPS_ALGO * N * N / (f["sweep_ms"] * 1e-3) / PEAK_FP64,
         }
     print(json.dumps(out), flush=True)
+
+
+def profiled_counters(kernel_variant_mixed):
+    """Per-launch HBM traffic and issued FLOPs of the sweep from the committed
+    rocprofv3 counter summary, if the sweep's sources are unchanged since it
+    was taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_n65536_traffic.json")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+        src = b""
+        for name in ("sweep.hip", "plan.h"):
+            with open(os.path.join(ROOT, "paper_1104_2700_amd", "csrc", name), "rb") as f:
+                src += f.read()
+        if hashlib.sha256(src).hexdigest() != prof.get("source_sha256"):
+            return None
+        return prof
+    except (OSError, ValueError):
+        return None
 
 
 def cpu_leg(x, v, m, eps2, results, target_s):
