@@ -208,9 +208,12 @@ int hermite_energy(hermite_ctx* ctx, const hermite_state* s,
 /* ---- whole steps, graphs and runs -------------------------------------- */
 
 /* One block step: select -> predict -> force -> correct, with T and n_act
- * kept on the device (context scratch).  With use_graph != 0 the four
- * stages are captured once into a HIP graph (per state/cluster/precision/
- * parameter set) and replayed.  Steps past T_end do nothing. */
+ * kept on the device (context scratch).  The prediction is fused into the
+ * sweep (each j as it is staged, each active i as it is loaded) and into
+ * the corrector, so a step touches only the particles the sweep reads;
+ * s->xp and s->vp are not written.  With use_graph != 0 the stages are
+ * captured once into a HIP graph (per state/cluster/precision/parameter
+ * set) and replayed.  Steps past T_end do nothing. */
 int hermite_step(hermite_ctx* ctx, const hermite_state* s,
                  const hermite_clusters* cl, double eps2, int precision,
                  const hermite_dt_params* p, int64_t T_end, int use_graph,

@@ -57,6 +57,17 @@ struct SweepArgs {
     int32_t ipl;               // active particles per lane (set by launch_force)
     // counters (may be null): [0] steps, [1] interactions, [4] last n_act
     int64_t* counters;
+    // On-the-fly prediction (block-step path): when pred_x is non-null the
+    // i and j particles are predicted from pred_x/v/a/j at block time
+    // *pred_T from their times pred_t (equations (xpred), (vpred)) instead
+    // of being read from xp, vp.
+    const double* pred_x;
+    const double* pred_v;
+    const double* pred_a;
+    const double* pred_j;
+    const int64_t* pred_t;
+    const int64_t* pred_T;
+    double tick;               // 2^-tick_bits
     // outputs of the reduce stage
     double* acc;               // [3][n_act_max]
     double* jerk;              // [3][n_act_max] or null
@@ -121,16 +132,16 @@ struct CorrectArgs {
     int k_max;
     double* crit_out;          // or null
     int64_t* counters;         // [2] += clamped, or null
+    int predict_i;             // 1: predict the active particle from x, v, a, j, t
+                               //    at T instead of reading xp, vp
 };
 
 hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
 
-// Fused block-step stages: selection + prediction of every particle + the
-// sweep plan in three launches (the last one fused), and the corrector
-// with the fixed-order reduction of the sweep's partial sums.
-hipError_t launch_step_select(int64_t n, int tick_bits, const double* x, const double* v,
-                              const double* a, const double* j, double* xp, double* vp,
-                              const int64_t* t, const int64_t* dt, int64_t T_end,
+// Fused block-step stages: selection and the sweep plan in two launches
+// (prediction is folded into the sweep and the corrector), and the
+// corrector with the fixed-order reduction of the sweep's partial sums.
+hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, int64_t T_end,
                               int32_t* idx, int32_t* n_act, int64_t* T, int64_t* block_min,
                               int32_t* block_cnt, int64_t* counters, uint32_t* ticket,
                               const SweepArgs& sa, hipStream_t st);

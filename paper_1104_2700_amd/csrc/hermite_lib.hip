@@ -265,8 +265,16 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, na, (int32_t)n, eps2, tu, out,
                         out + 3 * n, out + 6 * n, &a));
     a.ipl = (tu.variant & 1) ? 2 : 1;
-    HIP_OK(launch_step_select(n, s->tick_bits, s->x, s->v, s->a, s->j, s->xp, s->vp, s->t,
-                              s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
+    // prediction happens inside the sweep and the corrector (no pass over
+    // the whole state: only particles a sweep touches are predicted)
+    a.pred_x = s->x;
+    a.pred_v = s->v;
+    a.pred_a = s->a;
+    a.pred_j = s->j;
+    a.pred_t = s->t;
+    a.pred_T = T;
+    a.tick = std::ldexp(1.0, -s->tick_bits);
+    HIP_OK(launch_step_select(n, s->t, s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
                               (int32_t*)c->sel_cnt.p, counters, (uint32_t*)c->ticket.p, a,
                               st));
     HIP_OK(launch_sweep_only(a, precision, tu.variant, std::max(1, c->n_cu * tu.wg_per_cu),
@@ -293,6 +301,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.k_min = p->k_min;
     ca.k_max = p->k_max;
     ca.counters = counters;
+    ca.predict_i = 1;
     HIP_OK(launch_correct_reduce(ca, a, st));
     return HERMITE_OK;
 }

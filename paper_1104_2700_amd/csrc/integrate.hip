@@ -8,7 +8,7 @@
 namespace hm {
 namespace {
 
-constexpr int kSelPer = 4;                 // particles per thread in select
+constexpr int kSelPer = 16;                // particles per thread in select
 constexpr int kSelBlock = kWG * kSelPer;   // particles per select block
 
 // ---- block selection (procedure step 1) ---------------------------------
@@ -247,23 +247,17 @@ __global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t
     }
 }
 
-__global__ void __launch_bounds__(kWG) sel_write_predict_plan_kernel(
+__global__ void __launch_bounds__(kWG) sel_write_plan_kernel(
     int64_t n, const int64_t* t, const int64_t* dt, const int32_t* block_cnt, int nb,
     const int64_t* T_in, int64_t T_end, int32_t* idx, int32_t* n_act, int64_t* counters,
-    PredictArgs pa, SweepArgs sa, uint32_t* ticket)
+    SweepArgs sa, uint32_t* ticket)
 {
     __shared__ int32_t sh[kWG];
     __shared__ int32_t s_last;
+    __shared__ int32_t s_na;
     const int64_t T = *T_in;
     const bool live = T <= T_end;
-    const int32_t upto = sel_write_body(n, t, dt, block_cnt, T, live, idx, sh);
-    if (live) {
-        const int64_t base = (int64_t)blockIdx.x * kSelBlock;
-        for (int r = 0; r < kSelPer; ++r) {
-            const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
-            if (i < n) predict_one(n, i, T, t, pa);
-        }
-    }
+    (void)sel_write_body(n, t, dt, block_cnt, T, live, idx, sh);
     // the last block to arrive sees every block's indices
     __threadfence();
     __syncthreads();
@@ -271,12 +265,16 @@ __global__ void __launch_bounds__(kWG) sel_write_predict_plan_kernel(
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    __shared__ int32_t s_na;
+    int32_t part = 0;
+    for (int b = threadIdx.x; b < nb; b += kWG) part += block_cnt[b];
+    sh[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        int32_t tot = 0;
-        for (int b = 0; b < nb; ++b) tot += block_cnt[b];
-        const int32_t na = live ? tot : 0;
-        (void)upto;
+        const int32_t na = live ? sh[0] : 0;
         *n_act = na;
         count_step(counters, T, na);
         *ticket = 0u;
@@ -343,7 +341,24 @@ __device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double
     const int64_t dt_old = c.dt[i];
     const double h = (double)dt_old * tick;
     const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
-    double s1[3], cc[3];
+    double s1[3], cc[3], xp[3], vp[3];
+    if (c.predict_i) {
+        // equations (xpred), (vpred) for this particle, dt = T - t_i
+        const double hp = (double)(T - c.t[i]) * tick;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t o = d * n + i;
+            const double ac = c.a[o], jk = c.j[o];
+            xp[d] = fma(hp, fma(hp, fma(hp, jk * (1.0 / 6.0), ac * 0.5), c.v[o]), c.x[o]);
+            vp[d] = fma(hp, fma(hp, jk * 0.5, ac), c.v[o]);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xp[d] = c.xp[d * n + i];
+            vp[d] = c.vp[d * n + i];
+        }
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int64_t o = d * n + i;
@@ -352,8 +367,8 @@ __device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double
         const double da = a0 - a1;
         const double s0 = 2.0 * (-3.0 * da - (2.0 * j0 + j1) * h) / h2;
         const double c0 = 6.0 * (2.0 * da + (j0 + j1) * h) / h3;
-        c.x[o] = c.xp[o] + s0 * h4 / 24.0 + c0 * h5 / 120.0;
-        c.v[o] = c.vp[o] + s0 * h3 / 6.0 + c0 * h4 / 24.0;
+        c.x[o] = xp[d] + s0 * h4 / 24.0 + c0 * h5 / 120.0;
+        c.v[o] = vp[d] + s0 * h3 / 6.0 + c0 * h4 / 24.0;
         c.a[o] = a1;
         c.j[o] = j1;
         s1[d] = fma(c0, h, s0);
@@ -523,20 +538,17 @@ hipError_t launch_predict(int64_t n, int tick_bits, const double* x,
     return hipGetLastError();
 }
 
-hipError_t launch_step_select(int64_t n, int tick_bits, const double* x, const double* v,
-                              const double* a, const double* j, double* xp, double* vp,
-                              const int64_t* t, const int64_t* dt, int64_t T_end,
+hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, int64_t T_end,
                               int32_t* idx, int32_t* n_act, int64_t* T, int64_t* block_min,
                               int32_t* block_cnt, int64_t* counters, uint32_t* ticket,
                               const SweepArgs& sa, hipStream_t st)
 {
     const int nb = nblocks(n, kSelBlock);
-    PredictArgs pa{ldexp(1.0, -tick_bits), x, v, a, j, xp, vp};
     hipLaunchKernelGGL(sel_min_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min,
                        block_cnt, nb, T, ticket + 1);
-    hipLaunchKernelGGL(sel_write_predict_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+    hipLaunchKernelGGL(sel_write_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
                        (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
-                       counters, pa, sa, ticket);
+                       counters, sa, ticket);
     return hipGetLastError();
 }
 

@@ -49,51 +49,17 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
     __shared__ int32_t s_items[kWG];
     __shared__ int32_t s_cmax[kWG];
     __shared__ int64_t s_inter[kWG];
-    __shared__ int32_t s_na, s_L, s_ti;
+    __shared__ int32_t s_L, s_ti;
     __shared__ int64_t s_jc;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
-        // Work items wanted (about one per resident workgroup slot, times
-        // the tuning factor), and the most j-chunks a cluster can give
-        // (each chunk at least one LDS tile).
-        const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
-        // j-chunks available per active particle: each chunk at least one
-        // LDS tile, and all partial sums must fit the scratch buffer.
-        int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
-        if (na > 0) {
-            const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
-            if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
-        }
-        // Fewest lanes per particle that still yields enough items: more
-        // particles per item means more work per staged j tile.
-        int32_t L = 1;
-        for (; L < 64; L <<= 1) {
-            const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-            const int64_t tiles = (na + ti_l - 1) / ti_l;
-            if (tiles * s_cap >= want) break;
-        }
-        const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-        const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l : 1;
-        int64_t S = (want + tiles - 1) / tiles;
-        if (S > s_cap) S = s_cap;
-        if (S < 1) S = 1;
-        int64_t jc = (a.n_cmax + S - 1) / S;
-        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
-        if (jc < jmin) jc = jmin;
-        jc = (jc + kTJ - 1) / kTJ * kTJ;
-        // rounding jc up can only lower the chunk count, so the buffer fits
-        s_na = na; s_L = L; s_ti = a.ipl * (kWG / L); s_jc = jc;
-    }
-    __syncthreads();
-    const int32_t na = s_na, ti = s_ti;
-    const int64_t jc = s_jc;
+    const int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
     const int C = a.n_clusters;
     const int per = (C + kWG - 1) / kWG;
     const int c0 = tid * per;
     const int c1 = (c0 + per < C) ? c0 + per : C;
-    int32_t local = 0, cmax = 0;
-    int64_t inter = 0;
+
+    // 1. the active run of every cluster (idx is ascending)
+    int32_t nact_c = 0;
     for (int c = c0; c < c1; ++c) {
         const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
         const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
@@ -108,15 +74,72 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
             st = lower_bound_idx(a.idx, na, o0);
             cnt = lower_bound_idx(a.idx, na, o1) - st;
         }
-        const int32_t tiles = (cnt + ti - 1) / ti;
-        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
         a.act_start[c] = st;
         a.act_cnt[c] = cnt;
+        nact_c += cnt > 0 ? 1 : 0;
+    }
+    s_items[tid] = nact_c;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if (tid < s) s_items[tid] += s_items[tid + s];
+        __syncthreads();
+    }
+
+    // 2. the split: lanes per particle L and chunk length jc
+    if (tid == 0) {
+        const int64_t c_act = s_items[0] > 0 ? s_items[0] : 1;
+        // Work items wanted (about one per resident workgroup slot, times
+        // the tuning factor), and the most j-chunks a cluster can give
+        // (each chunk at least one LDS tile, all partial sums in the buffer).
+        const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
+        int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
+        if (na > 0) {
+            const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
+            if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
+        }
+        // Fewest lanes per particle that (a) still yields enough items and
+        // (b) keeps tiles at least half full given the active particles
+        // per active cluster: more particles per item means more work per
+        // staged j tile, but a tile larger than a cluster's active run
+        // leaves lanes idle.
+        const int64_t per_cluster = (na + c_act - 1) / c_act;
+        int32_t L = 1;
+        for (; L < 64; L <<= 1) {
+            const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+            const int64_t tiles = (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0);
+            if (tiles * s_cap >= want && ti_l <= 2 * per_cluster) break;
+        }
+        const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+        const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0) : 1;
+        int64_t S = (want + tiles - 1) / tiles;
+        if (S > s_cap) S = s_cap;
+        if (S < 1) S = 1;
+        int64_t jc = (a.n_cmax + S - 1) / S;
+        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
+        if (jc < jmin) jc = jmin;
+        jc = (jc + kTJ - 1) / kTJ * kTJ;
+        // rounding jc up can only lower the chunk count, so the buffer fits
+        s_L = L; s_ti = (int32_t)ti_l; s_jc = jc;
+    }
+    __syncthreads();
+    const int32_t ti = s_ti;
+    const int64_t jc = s_jc;
+
+    // 3. work items per cluster and their offsets
+    int32_t local = 0, cmax = 0;
+    int64_t inter = 0;
+    for (int c = c0; c < c1; ++c) {
+        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
+        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
+        const int32_t cnt = a.act_cnt[c];
+        const int32_t tiles = (cnt + ti - 1) / ti;
+        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
         a.chunks[c] = ch;
         local += tiles * ch;
         cmax = ch > cmax ? ch : cmax;
         inter += (int64_t)cnt * (o1 - o0);
     }
+    __syncthreads();
     s_items[tid] = local;
     s_cmax[tid] = cmax;
     s_inter[tid] = inter;
@@ -152,7 +175,6 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         }
     }
 }
-
 
 __device__ inline int cluster_of(const SweepArgs& a, int p)
 {
@@ -190,6 +212,31 @@ __device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, i
 #pragma unroll
     for (int q = 0; q < 7; ++q)
         for (int o = 1; o < 64; o <<= 1) out[q] += __shfl_xor(out[q], o);
+}
+
+// Position and velocity of particle i for the sweep: predicted on the fly
+// (Taylor predictor, equations (xpred), (vpred), Horner form with FMA) or
+// read from the predicted arrays.
+__device__ inline void fetch_particle(const SweepArgs& a, int64_t i, int64_t T, double r[3],
+                                      double w[3])
+{
+    const int64_t n = a.n;
+    if (a.pred_x) {
+        const double h = (double)(T - a.pred_t[i]) * a.tick;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t o = d * n + i;
+            const double ac = a.pred_a[o], jk = a.pred_j[o];
+            r[d] = fma(h, fma(h, fma(h, jk * (1.0 / 6.0), ac * 0.5), a.pred_v[o]), a.pred_x[o]);
+            w[d] = fma(h, fma(h, jk * 0.5, ac), a.pred_v[o]);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r[d] = a.xp[d * n + i];
+            w[d] = a.vp[d * n + i];
+        }
+    }
 }
 
 // Chunk counts above this use the wave-per-particle reduction.

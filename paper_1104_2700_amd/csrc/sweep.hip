@@ -377,12 +377,14 @@ __device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int6
                                             const I64 (&I)[IPL], double eps2,
                                             SumF (&F)[IPL], RUN (&S)[IPL])
 {
-    const int64_t n = a.n;
     const float eps2f = (float)eps2;
+    const int64_t T = a.pred_x ? *a.pred_T : 0;
     int run = 0;
     for (int64_t jj = j0 + lane; jj < j1; jj += 64) {
-        const double xj = a.xp[jj], yj = a.xp[n + jj], zj = a.xp[2 * n + jj];
-        const double vxj = a.vp[jj], vyj = a.vp[n + jj], vzj = a.vp[2 * n + jj];
+        double r[3], w[3];
+        fetch_particle(a, jj, T, r, w);
+        const double xj = r[0], yj = r[1], zj = r[2];
+        const double vxj = w[0], vyj = w[1], vzj = w[2];
         const double mj = a.m[jj];
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
@@ -438,6 +440,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     const int sub = tid & (L - 1);
     const int C = a.n_clusters;
     const int64_t n = a.n;
+    const int64_t Tpred = a.pred_x ? *a.pred_T : 0;
 
     // Workgroup w starts with item w; only when there are more items than
     // workgroups do the finished ones take further items from the counter.
@@ -472,9 +475,10 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             valid[q] = pos < pcnt;
             pp[q] = p0 + (valid[q] ? pos : 0);
             ii[q] = a.idx ? a.idx[pp[q]] : pp[q];
-            const int i = ii[q];
-            I[q].x = a.xp[i]; I[q].y = a.xp[n + i]; I[q].z = a.xp[2 * n + i];
-            I[q].vx = a.vp[i]; I[q].vy = a.vp[n + i]; I[q].vz = a.vp[2 * n + i];
+            double r[3], w[3];
+            fetch_particle(a, ii[q], Tpred, r, w);
+            I[q].x = r[0]; I[q].y = r[1]; I[q].z = r[2];
+            I[q].vx = w[0]; I[q].vy = w[1]; I[q].vz = w[2];
             if constexpr (SPLIT) {
                 split(I[q].x, IS[q].xh, IS[q].xl);
                 split(I[q].y, IS[q].yh, IS[q].yl);
@@ -498,23 +502,30 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             __syncthreads();
             if (tid < cnt) {
                 const int64_t jg = tb + tid;
-                if constexpr (SPLIT) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        split(a.xp[d * n + jg], T.c[2 * d][tid], T.c[2 * d + 1][tid]);
-                        split(a.vp[d * n + jg], T.c[6 + 2 * d][tid], T.c[7 + 2 * d][tid]);
-                    }
-                    T.m[tid] = (float)a.m[jg];
-                } else {
+                if constexpr (POT_ONLY) {
                     T.x[tid] = a.xp[jg];
                     T.y[tid] = a.xp[n + jg];
                     T.z[tid] = a.xp[2 * n + jg];
-                    if (!POT_ONLY) {
-                        T.vx[tid] = a.vp[jg];
-                        T.vy[tid] = a.vp[n + jg];
-                        T.vz[tid] = a.vp[2 * n + jg];
-                    }
                     T.m[tid] = (MT)a.m[jg];
+                } else {
+                    double r[3], w[3];
+                    fetch_particle(a, jg, Tpred, r, w);
+                    if constexpr (SPLIT) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            split(r[d], T.c[2 * d][tid], T.c[2 * d + 1][tid]);
+                            split(w[d], T.c[6 + 2 * d][tid], T.c[7 + 2 * d][tid]);
+                        }
+                        T.m[tid] = (float)a.m[jg];
+                    } else {
+                        T.x[tid] = r[0];
+                        T.y[tid] = r[1];
+                        T.z[tid] = r[2];
+                        T.vx[tid] = w[0];
+                        T.vy[tid] = w[1];
+                        T.vz[tid] = w[2];
+                        T.m[tid] = (MT)a.m[jg];
+                    }
                 }
             }
             __syncthreads();

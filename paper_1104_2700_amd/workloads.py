@@ -24,7 +24,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import sys
 import time
 
@@ -155,7 +154,8 @@ def c3(ctx, t_end=1.0):
     return {"config": "plummer_n65536_mixed", "latency_curve": curve, "run": run}
 
 
-def c4(ctx, t_end=0.5, serial_t_end=None, n_clusters=256):
+def c4(ctx, t_end=0.5, serial_t_end=0.125, n_clusters=256, serial_clusters=16):
+    """Batched ensemble run, then batched vs serial on a subset of clusters."""
     x, v, m, off, eps = inputs.ensemble(n_clusters, 4)
     eps2 = eps ** 2
     sizes = np.diff(off)
@@ -170,18 +170,22 @@ def c4(ctx, t_end=0.5, serial_t_end=None, n_clusters=256):
     out["tuning"] = ctx.autotune(s, 0.0, H.MIXED, int(off[-1]), clusters=cl).as_dict()
     ctx.initialize(s, 0.0, p, H.MIXED, clusters=cl)
     out["batched"] = block_run(ctx, s, 0.0, p, t_end, H.MIXED, clusters=cl, label="c4 batched")
-    # serial loop: every cluster integrated on its own, one after another
-    st_end = t_end if serial_t_end is None else serial_t_end
-    if st_end > 0:
-        sb = H.State(x, v, m, TB)
-        ctx.initialize(sb, 0.0, p, H.MIXED, clusters=cl)
-        out["batched_short"] = block_run(ctx, sb, 0.0, p, st_end, H.MIXED, clusters=cl,
-                                         label="c4 batched(short)")
+    # the same clusters, one system at a time, against the batched ensemble
+    # of those clusters (a subset keeps the serial loop short)
+    if serial_t_end and serial_clusters > 0:
+        k = min(serial_clusters, n_clusters)
+        hi_all = int(off[k])
+        sub_off = off[:k + 1]
+        cls = H.Clusters(sub_off, eps2[:k])
+        sb = H.State(x[:, :hi_all], v[:, :hi_all], m[:hi_all], TB)
+        ctx.initialize(sb, 0.0, p, H.MIXED, clusters=cls)
+        bs = block_run(ctx, sb, 0.0, p, serial_t_end, H.MIXED, clusters=cls,
+                       label="c4 batched(subset)")
         torch.cuda.synchronize()
-        T_end = int(round(st_end * (1 << TB)))
+        T_end = int(round(serial_t_end * (1 << TB)))
         t0 = time.perf_counter()
         steps = inter = 0
-        for c in range(n_clusters):
+        for c in range(k):
             lo, hi = int(off[c]), int(off[c + 1])
             sc = H.State(x[:, lo:hi], v[:, lo:hi], m[lo:hi], TB)
             ctx.initialize(sc, float(eps2[c]), p, H.MIXED)
@@ -189,14 +193,14 @@ def c4(ctx, t_end=0.5, serial_t_end=None, n_clusters=256):
                              sync_every=256)
             steps += st
             inter += it
-            if c % 32 == 31:
-                _log("  c4 serial: %d clusters done, %.1f s" % (c + 1, time.perf_counter() - t0))
+            _log("  c4 serial: cluster %d/%d done, %.1f s" % (c + 1, k, time.perf_counter() - t0))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out["serial"] = {"t_end": st_end, "wall_s": wall, "block_steps": steps,
-                         "interactions": inter, "interactions_per_s": inter / wall,
-                         "gflops_60": 60 * inter / wall / 1e9}
-        out["batched_vs_serial_speedup"] = wall / out["batched_short"]["wall_s"]
+        out["subset"] = {"clusters": k, "t_end": serial_t_end, "batched": bs,
+                         "serial": {"wall_s": wall, "block_steps": steps, "interactions": inter,
+                                    "interactions_per_s": inter / wall,
+                                    "gflops_60": 60 * inter / wall / 1e9},
+                         "batched_vs_serial_speedup": wall / bs["wall_s"]}
     return out
 
 
@@ -219,6 +223,7 @@ def main(argv=None):
     ap.add_argument("name", choices=sorted(RUNNERS))
     ap.add_argument("--t-end", type=float, default=None)
     ap.add_argument("--serial-t-end", type=float, default=None)
+    ap.add_argument("--serial-clusters", type=int, default=None)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     ctx = H.Context(0)
@@ -227,6 +232,8 @@ def main(argv=None):
         kw["t_end"] = a.t_end
     if a.name == "c4" and a.serial_t_end is not None:
         kw["serial_t_end"] = a.serial_t_end
+    if a.name == "c4" and a.serial_clusters is not None:
+        kw["serial_clusters"] = a.serial_clusters
     _log("workload %s %s" % (a.name, kw))
     res = RUNNERS[a.name](ctx, **kw)
     res["device"] = torch.cuda.get_device_name(0)
