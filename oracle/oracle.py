@@ -59,7 +59,7 @@ def configure(lib):
     lib.oracle_correct.argtypes = ([i64, i64, P, i64, i32] + [P] * 5
                                    + [P] * 7 + [d, i32, i32, i32, P])
     lib.oracle_correct.restype = i64
-    lib.oracle_init_dt.argtypes = [i64, P, P, P, P, i32, d, i32, i32, i32]
+    lib.oracle_init_dt.argtypes = [i64, P, P, P, P, i32, d, i32, d, i32, i32]
     lib.oracle_init_dt.restype = i64
     lib.oracle_energy.argtypes = [i64, P, P, P, d, P, P, P, P, P, P]
     lib.oracle_energy.restype = None
@@ -150,13 +150,14 @@ def quantize(dt_crit, k_old, T, tick_bits, k_min, k_max):
     return int(dt), k.value, cl.value
 
 
-def init_dt(state, eta, form, k_min, k_max):
-    """First step sizes from |a|/|j| (t_i = 0); returns the clamped count."""
+def init_dt(state, eta, form, k_min, k_max, eta_init=0.0):
+    """First step sizes eta_s |a|/|j| (t_i = 0; eta_s = eta_init, or the
+    steady factor / 16 when eta_init is 0); returns the clamped count."""
     n = state["m"].shape[0]
     return int(_L().oracle_init_dt(n, _p(state["a"]), _p(state["j"]),
                                    _p(state["t"]), _p(state["dt"]),
                                    int(state["tick_bits"]), float(eta), int(form),
-                                   int(k_min), int(k_max)))
+                                   float(eta_init), int(k_min), int(k_max)))
 
 
 def correct(state, idx, T, xp, vp, acc1, jrk1, pot1, eta, form, k_min, k_max,
@@ -202,7 +203,7 @@ def new_state(x, v, m, tick_bits):
     }
 
 
-def initialize(state, eps2, eta, form, k_min, k_max):
+def initialize(state, eps2, eta, form, k_min, k_max, eta_init=0.0):
     """t = 0: a full sweep gives a0, j0, pot; then the first step sizes."""
     n = state["m"].shape[0]
     acc, jrk, pot = force(state["x"], state["v"], state["m"],
@@ -210,7 +211,7 @@ def initialize(state, eps2, eta, form, k_min, k_max):
     state["a"][...] = acc
     state["j"][...] = jrk
     state["pot"][...] = pot
-    return init_dt(state, eta, form, k_min, k_max)
+    return init_dt(state, eta, form, k_min, k_max, eta_init)
 
 
 def block_step(state, eps2, eta, form, k_min, k_max, T_end=None):

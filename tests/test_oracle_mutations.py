@@ -45,6 +45,8 @@ MUTANTS = [
     ("growth limit dropped", "if (k_old >= 0 && k < k_old - 1) k = k_old - 1;", ""),
     ("commensurability dropped", "while (k < k_max && (T & ((((int64_t)1) << (tick_bits - k)) - 1)) != 0)",
      "while (0)"),
+    ("start-up divisor dropped", "eta_init : eta_f / 16.0;", "eta_init : eta_f;"),
+    ("start-up uses |j|/|a|", "const double crit = eta_s * A / J;", "const double crit = eta_s * J / A;"),
     ("select picks t_i = T", "if (t[i] + dt[i] == T) idx[k++]", "if (t[i] == T) idx[k++]"),
     ("energy W without 1/2", "nsum_add(&w, 0.5 * m[i] * phi_scratch[i]);",
      "nsum_add(&w, m[i] * phi_scratch[i]);"),
@@ -71,6 +73,8 @@ PINS = [
     P.test_quantize_examples,
     P.test_select_definition,
     P.test_energy_matches_pot_sweep,
+    P.test_init_dt_examples,
+    P.test_startup_transient_below_integration_error,
     lambda: P.test_kepler_orbit_fourth_order(0.5),
 ]
 
