@@ -279,14 +279,12 @@ int64_t oracle_correct(int64_t n, int64_t n_act, const int32_t* idx,
 }
 
 /* ------------------------------------------------------------------ */
-/* First step (the paper does not give one; this is a reading): no     */
-/* snap or crackle exists yet, so dt0 = eta_s |a| / |j|, quantised     */
-/* with T = 0 and no growth limit.  |a|/|j| has no guard against a     */
-/* jerk that happens to be small, so the start-up factor eta_s is      */
-/* smaller than the steady one: eta_s = eta_init if eta_init > 0, else */
-/* eta_f / 16 with eta_f = eta (form 0) or sqrt(eta) (form 1).  The    */
-/* growth limit (at most 2x per step) reaches the steady step within   */
-/* four steps.  Sets t_i = 0.                                          */
+/* First step (the paper gives none; reading: dt0 = eta_f |a| / |j|    */
+/* with eta_f = eta (form 0) or sqrt(eta) (form 1), quantised with     */
+/* T = 0 and no growth limit).  eta_init > 0 replaces eta_f: |a|/|j|   */
+/* has no guard against a small initial jerk, and a smaller start-up   */
+/* factor keeps the first step from dominating a run's energy error.   */
+/* Sets t_i = 0.                                                       */
 /* ------------------------------------------------------------------ */
 int64_t oracle_init_dt(int64_t n, const double* acc, const double* jrk,
                        int64_t* t, int64_t* dt, int tick_bits,
@@ -294,7 +292,7 @@ int64_t oracle_init_dt(int64_t n, const double* acc, const double* jrk,
 {
     int64_t n_clamped = 0;
     const double eta_f = form == 0 ? eta : sqrt(eta);
-    const double eta_s = eta_init > 0.0 ? eta_init : eta_f / 16.0;
+    const double eta_s = eta_init > 0.0 ? eta_init : eta_f;
     for (int64_t i = 0; i < n; ++i) {
         const double A = norm3(acc[i], acc[n + i], acc[2 * n + i]);
         const double J = norm3(jrk[i], jrk[n + i], jrk[2 * n + i]);

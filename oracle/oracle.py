@@ -152,7 +152,8 @@ def quantize(dt_crit, k_old, T, tick_bits, k_min, k_max):
 
 def init_dt(state, eta, form, k_min, k_max, eta_init=0.0):
     """First step sizes eta_s |a|/|j| (t_i = 0; eta_s = eta_init, or the
-    steady factor / 16 when eta_init is 0); returns the clamped count."""
+    steady factor eta / sqrt(eta) when eta_init is 0); returns the
+    clamped count."""
     n = state["m"].shape[0]
     return int(_L().oracle_init_dt(n, _p(state["a"]), _p(state["j"]),
                                    _p(state["t"]), _p(state["dt"]),

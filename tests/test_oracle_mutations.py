@@ -45,7 +45,9 @@ MUTANTS = [
     ("growth limit dropped", "if (k_old >= 0 && k < k_old - 1) k = k_old - 1;", ""),
     ("commensurability dropped", "while (k < k_max && (T & ((((int64_t)1) << (tick_bits - k)) - 1)) != 0)",
      "while (0)"),
-    ("start-up divisor dropped", "eta_init : eta_f / 16.0;", "eta_init : eta_f;"),
+    ("explicit start-up factor ignored", "eta_init > 0.0 ? eta_init : eta_f;", "eta_f;"),
+    ("start-up uses eta for form 1", "form == 0 ? eta : sqrt(eta);\n    const double eta_s",
+     "eta;\n    const double eta_s"),
     ("start-up uses |j|/|a|", "const double crit = eta_s * A / J;", "const double crit = eta_s * J / A;"),
     ("select picks t_i = T", "if (t[i] + dt[i] == T) idx[k++]", "if (t[i] == T) idx[k++]"),
     ("energy W without 1/2", "nsum_add(&w, 0.5 * m[i] * phi_scratch[i]);",

@@ -405,30 +405,32 @@ def test_kepler_high_eccentricity_conserves_energy():
 
 
 def test_init_dt_examples():
-    """Start-up step eta_s |a|/|j| with eta_s = steady factor / 16 unless
-    given, quantised to the largest 2^-k not above it (worked by hand)."""
+    """Start-up step eta_s |a|/|j|, eta_s = the steady factor unless given,
+    quantised to the largest 2^-k not above it (worked by hand)."""
     st_ = O.new_state(np.zeros((3, 2)), np.zeros((3, 2)), np.ones(2), 20)
     st_["a"][:, 0] = (1.0, 0.0, 0.0)
     st_["j"][:, 0] = (0.0, 2.0, 0.0)
     st_["a"][:, 1] = (0.0, 3.0, 4.0)      # |a| = 5
     st_["j"][:, 1] = (0.0, 0.0, 0.1)      # |a|/|j| = 50
-    # form 0, eta 0.02: 0.02/16 * 0.5 = 6.25e-4 -> 2^-11; 0.02/16 * 50 = 0.0625 -> 2^-4
-    O.init_dt(st_, 0.02, O.FORM_PAPER, 3, 20)
-    assert list(st_["dt"]) == [1 << 9, 1 << 16] and list(st_["t"]) == [0, 0]
-    # form 1, eta 0.04: sqrt(0.04)/16 * 0.5 = 6.25e-3 -> 2^-8; * 50 = 0.625 -> capped
-    # at the largest step 2^-3 (not a clamp: clamps count steps forced below 2^-k_max)
-    assert O.init_dt(st_, 0.04, O.FORM_AARSETH, 3, 20) == 0
-    assert list(st_["dt"]) == [1 << 12, 1 << 17]
-    # explicit factor 0.1: 0.05 -> 2^-5; 5.0 -> capped at 2^-3
+    # form 0, eta 0.02: 0.02 * 0.5 = 0.01 -> 2^-7; 0.02 * 50 = 1 -> capped at 2^-3
+    # (not a clamp: clamps count steps forced below 2^-k_max)
+    assert O.init_dt(st_, 0.02, O.FORM_PAPER, 3, 20) == 0
+    assert list(st_["dt"]) == [1 << 13, 1 << 17] and list(st_["t"]) == [0, 0]
+    # form 1, eta 0.04: sqrt(0.04) * 0.5 = 0.1 -> 2^-4; * 50 = 10 -> 2^-3
+    O.init_dt(st_, 0.04, O.FORM_AARSETH, 3, 20)
+    assert list(st_["dt"]) == [1 << 16, 1 << 17]
+    # explicit factor 0.1: 0.05 -> 2^-5; 5.0 -> 2^-3; 0.001: 5e-4 -> 2^-11; 0.05 -> 2^-5
     O.init_dt(st_, 0.02, O.FORM_PAPER, 3, 20, eta_init=0.1)
     assert list(st_["dt"]) == [1 << 15, 1 << 17]
+    O.init_dt(st_, 0.02, O.FORM_PAPER, 3, 20, eta_init=0.001)
+    assert list(st_["dt"]) == [1 << 9, 1 << 15]
 
 
 def test_startup_transient_below_integration_error():
-    """The first step has no snap/crackle guard; the default start-up
-    factor keeps its error below the integration error, so a 4x smaller
-    start changes the energy error at t = 1/8 by < 10 %, whereas the
-    unreduced factor (eta_s = eta) dominates the error by > 100x."""
+    """The first step has no snap/crackle guard: with the steady factor
+    (eta_s = eta) it dominates the energy error at t = 1/8 by > 100x; with
+    eta/16 the start-up is below the integration error, so a further 4x
+    smaller start changes the error by < 10 %."""
     x, v, m = inputs.plummer(128, 31)
     eps2 = (1.0 / 64) ** 2
     eta = 0.02
@@ -441,22 +443,24 @@ def test_startup_transient_below_integration_error():
         K1, W1 = O.energy(st_["x"], st_["v"], m, eps2)
         return abs((K1 + W1) - (K0 + W0)) / abs(K0 + W0)
 
-    e_def, e_small, e_big = err(0.0), err(eta / 64), err(eta)
-    assert abs(e_def - e_small) < 0.1 * e_small, (e_def, e_small)
-    assert e_big > 100.0 * e_small, (e_big, e_small)
+    e_16, e_64, e_def = err(eta / 16), err(eta / 64), err(0.0)
+    assert abs(e_16 - e_64) < 0.1 * e_64, (e_16, e_64)
+    assert e_def > 100.0 * e_64, (e_def, e_64)
 
 
 def test_plummer_block_run_energy_drift():
-    """Block-timestep run of a small Plummer sphere: energy conserved to a
+    """Block-timestep run of a small Plummer sphere (start-up factor eta/16,
+    so the start-up transient does not dominate): energy conserved to a
     level that shrinks with eta as a fourth-order scheme's does (2^4 per
-    halving; a start-up dominated error would fall as 2^5)."""
+    halving; a start-up dominated error falls as ~2^5)."""
     x, v, m = inputs.plummer(128, 31)
     eps2 = (1.0 / 64) ** 2
     drifts = []
     for eta in (0.02, 0.01):
         st_ = O.new_state(x, v, m, 20)
         K0, W0 = O.energy(st_["x"], st_["v"], m, eps2)
-        stats = O.run(st_, 1 << 17, eps2, eta, O.FORM_PAPER, 3, 20)
+        O.initialize(st_, eps2, eta, O.FORM_PAPER, 3, 20, eta_init=eta / 16)
+        stats = O.run(st_, 1 << 17, eps2, eta, O.FORM_PAPER, 3, 20, init=False)
         assert np.all(st_["t"] == 1 << 17)
         K1, W1 = O.energy(st_["x"], st_["v"], m, eps2)
         drifts.append(abs((K1 + W1) - (K0 + W0)) / abs(K0 + W0))
