@@ -58,6 +58,11 @@ extern "C" {
 /* As HERMITE_MIXED, but the running sums are two-float (FP32 hi + lo,    */
 /* compensated by TwoSum) instead of FP64.                                */
 #define HERMITE_MIXED_2F  2
+/* Section 3.2 precision split as printed: FP64 relative position, FP32   */
+/* velocities and FP32 velocity difference, FP32 pair arithmetic, FP64    */
+/* sums of acc and pot, and the jerk summed in FP32 (over each j-chunk;   */
+/* chunk sums are added in FP64).                                         */
+#define HERMITE_MIXED_SP  3
 
 /* ---- timestep criterion forms (Section 2, eq. (timestep)) ------------ */
 #define HERMITE_DT_PAPER    0  /* dt = eta * sqrt(R), as printed          */
@@ -90,6 +95,8 @@ typedef struct hermite_dt_params {
     int32_t k_min;        /* largest step 2^-k_min, k_min >= 0            */
     int32_t k_max;        /* smallest step 2^-k_max, k_max <= tick_bits   */
     int32_t reserved0;
+    double  eta_init;     /* start-up factor of hermite_init_dt; 0 selects */
+                          /* the steady factor, else > 0                   */
 } hermite_dt_params;
 
 /* Independent clusters in one state (ensembles).  Particles of cluster c
@@ -110,7 +117,9 @@ typedef struct hermite_tuning {
     int32_t target_lanes;     /* lanes the j-split aims to keep busy      */
     int32_t wg_per_cu;        /* persistent workgroups per compute unit   */
     int32_t min_j_per_lane;   /* smallest j-run a lane is given per chunk */
-    int32_t variant;          /* inner-loop variant (0 = default)         */
+    int32_t variant;          /* inner loop, 0..3: bit 0 = two active     */
+                              /* particles per lane; bit 1 = FP32 hi/lo   */
+                              /* split differences (MIXED, MIXED_2F only) */
 } hermite_tuning;
 
 typedef struct hermite_ctx hermite_ctx;
@@ -162,7 +171,8 @@ int hermite_predict(hermite_ctx* ctx, const hermite_state* s,
  * n_act_max == n).  n_act_dev: device count, or NULL for n_act_max.
  * Outputs (device): acc [3][n_act_max], jerk [3][n_act_max],
  * pot [n_act_max] (may be NULL); only the first n_act columns written.
- * precision: HERMITE_FP64 / HERMITE_MIXED / HERMITE_MIXED_2F.
+ * precision: HERMITE_FP64 / HERMITE_MIXED / HERMITE_MIXED_2F /
+ * HERMITE_MIXED_SP.
  * Results are bitwise reproducible run to run for a fixed tuning. */
 int hermite_force_jerk(hermite_ctx* ctx, const hermite_state* s,
                        const hermite_clusters* cl,
@@ -184,9 +194,14 @@ int hermite_correct(hermite_ctx* ctx, const hermite_state* s,
                     const hermite_dt_params* p, double* crit_out,
                     void* stream);
 
-/* First step sizes (no snap or crackle yet): dt0 = eta_f |a| / |j| with
- * eta_f = eta (paper form) or sqrt(eta) (classic form), quantised at
- * T = 0; sets t_i = 0.  Reads s->a, s->j. */
+/* First step sizes (no snap or crackle yet; the paper gives no start-up
+ * rule): dt0 = eta_s |a| / |j|, quantised at T = 0 with no growth limit;
+ * sets t_i = 0.  eta_s = p->eta_init if > 0, else eta_f = eta (paper
+ * form) or sqrt(eta) (classic form).  |a|/|j| has no guard against a small
+ * initial jerk: with eta_s = eta_f the first step can dominate a run's
+ * energy error, and eta_init = eta_f / 16 keeps it below the integration
+ * error (the 2x growth limit then reaches the steady step in four steps).
+ * Reads s->a, s->j. */
 int hermite_init_dt(hermite_ctx* ctx, const hermite_state* s,
                     const hermite_dt_params* p, void* stream);
 

@@ -151,7 +151,7 @@ hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipS
 
 hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,
                           const double* j, int64_t* t, int64_t* dt,
-                          double eta, int form, int k_min, int k_max,
+                          double eta, int form, double eta_init, int k_min, int k_max,
                           int64_t* counters, hipStream_t st);
 
 hipError_t launch_copy2(int64_t count, const double* src0, double* dst0,

@@ -65,7 +65,7 @@ struct hermite_ctx {
     int n_cu = 0;
     std::string arch;
     hipStream_t cap_stream = nullptr;
-    hermite_tuning tuning[3];
+    hermite_tuning tuning[4];
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     Buf sel_min, sel_cnt;
@@ -127,7 +127,7 @@ int check_state(const hermite_state* s)
 
 int check_precision(int precision)
 {
-    if (precision < HERMITE_FP64 || precision > HERMITE_MIXED_2F)
+    if (precision < HERMITE_FP64 || precision > HERMITE_MIXED_SP)
         return fail(HERMITE_EINVAL, "unknown precision %d", precision);
     return HERMITE_OK;
 }
@@ -154,6 +154,8 @@ int check_dt(const hermite_dt_params* p, int tick_bits)
 {
     if (!p) return fail(HERMITE_EINVAL, "null dt params");
     if (!(p->eta > 0.0) || std::isinf(p->eta)) return fail(HERMITE_EINVAL, "eta must be > 0");
+    if (!(p->eta_init >= 0.0) || std::isinf(p->eta_init))
+        return fail(HERMITE_EINVAL, "eta_init must be >= 0 (0 = default)");
     if (p->form != HERMITE_DT_PAPER && p->form != HERMITE_DT_AARSETH)
         return fail(HERMITE_EINVAL, "unknown timestep form %d", p->form);
     if (p->k_min < 0 || p->k_max < p->k_min || p->k_max > tick_bits)
@@ -359,7 +361,7 @@ int hermite_create(int device, hermite_ctx** out)
         delete c;
         return fail(HERMITE_EHIP, "hipStreamCreateWithFlags failed");
     }
-    for (int p = 0; p < 3; ++p) c->tuning[p] = default_tuning(c, p);
+    for (int p = 0; p < 4; ++p) c->tuning[p] = default_tuning(c, p);
     int rc = ensure(c, c->counters, sizeof(int64_t) * kCounters);
     if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * kCounters) != hipSuccess)
         rc = fail(HERMITE_EHIP, "hipMemset of counters failed");
@@ -496,7 +498,7 @@ int hermite_init_dt(hermite_ctx* c, const hermite_state* s, const hermite_dt_par
     CHECK(check_state(s));
     CHECK(check_dt(p, s->tick_bits));
     HIP_OK(launch_init_dt(s->n, s->tick_bits, s->a, s->j, s->t, s->dt, p->eta, p->form,
-                          p->k_min, p->k_max, (int64_t*)c->counters.p, (hipStream_t)stream));
+                          p->eta_init, p->k_min, p->k_max, (int64_t*)c->counters.p, (hipStream_t)stream));
     return HERMITE_OK;
 }
 
@@ -517,7 +519,7 @@ int hermite_initialize(hermite_ctx* c, const hermite_state* s, const hermite_clu
                         s->a, s->j, s->pot, &a));
     CHECK(run_force(c, a, precision, tu, false, st));
     HIP_OK(launch_init_dt(s->n, s->tick_bits, s->a, s->j, s->t, s->dt, p->eta, p->form,
-                          p->k_min, p->k_max, (int64_t*)c->counters.p, st));
+                          p->eta_init, p->k_min, p->k_max, (int64_t*)c->counters.p, st));
     return HERMITE_OK;
 }
 
@@ -852,7 +854,7 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
         for (int q = 0; q < 3; ++q) limit[q] = std::max(tol, 1.5 * e[q]);
         const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{4}
                                                    : std::vector<int>{4, 16, 64};
-        const int nvar = precision == HERMITE_FP64 ? 2 : 4;
+        const int nvar = (precision == HERMITE_FP64 || precision == HERMITE_MIXED_SP) ? 2 : 4;
         for (int var = 0; var < nvar && rc == HERMITE_OK; ++var) {
             for (int w = 2; w <= 8 && rc == HERMITE_OK; ++w) {
                 for (int f : {1, 2, 4, 8}) {

@@ -438,14 +438,14 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
 __global__ void __launch_bounds__(kWG) init_dt_kernel(int64_t n, int tick_bits,
                                                       const double* a, const double* j,
                                                       int64_t* t, int64_t* dt,
-                                                      double eta_f, int k_min,
+                                                      double eta_s, int k_min,
                                                       int k_max, int64_t* counters)
 {
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (i >= n) return;
     const double A = norm3(a[i], a[n + i], a[2 * n + i]);
     const double J = norm3(j[i], j[n + i], j[2 * n + i]);
-    const double crit = eta_f * A / J;
+    const double crit = eta_s * A / J;
     int cl;
     t[i] = 0;
     dt[i] = quantize_dt(crit, -1, 0, tick_bits, k_min, k_max, &cl);
@@ -568,12 +568,15 @@ hipError_t launch_correct(const CorrectArgs& c, hipStream_t st)
 
 hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,
                           const double* j, int64_t* t, int64_t* dt,
-                          double eta, int form, int k_min, int k_max,
+                          double eta, int form, double eta_init, int k_min, int k_max,
                           int64_t* counters, hipStream_t st)
 {
+    // start-up factor: the steady one unless the caller gives a smaller one
+    // (|a|/|j| has no guard against a small initial jerk)
     const double eta_f = form == 0 ? eta : sqrt(eta);
+    const double eta_s = eta_init > 0.0 ? eta_init : eta_f;
     hipLaunchKernelGGL(init_dt_kernel, dim3(nblocks(n, kWG)), dim3(kWG), 0, st, n,
-                       tick_bits, a, j, t, dt, eta_f, k_min, k_max, counters);
+                       tick_bits, a, j, t, dt, eta_s, k_min, k_max, counters);
     return hipGetLastError();
 }
 

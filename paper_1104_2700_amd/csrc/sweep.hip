@@ -33,6 +33,10 @@
 //           sums added to FP64 running sums.
 //  MIXED_2F as MIXED, with the running sums held as two FP32 words
 //           (hi + lo) updated by Knuth's TwoSum.
+//  MIXED_SP the precision split of Section 3.2 as printed: r subtracted in
+//           FP64, velocities rounded to FP32 and subtracted in FP32, the
+//           acceleration and potential summed as in MIXED, the jerk kept in
+//           one FP32 running sum per lane for the whole j-range.
 #include "hermite_internal.h"
 #include "plan.h"
 
@@ -221,6 +225,46 @@ __device__ __forceinline__ void pair_split(const I32S& I, float eps2f, const flo
     S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
 }
 
+// Paper-faithful mixed term (Section 3.2 as printed): velocities held in
+// FP32 and their difference taken in FP32; everything else as pair_mixed.
+struct I64SP {  // i-particle: FP64 position, FP32 velocity
+    double x, y, z;
+    float vx, vy, vz;
+};
+
+template <bool MASK>
+__device__ __forceinline__ void pair_sp(const I64SP& I, float eps2f, double xj, double yj,
+                                        double zj, float vxj, float vyj, float vzj, float mj,
+                                        bool self, SumF& S)
+{
+    const float dx = (float)(xj - I.x), dy = (float)(yj - I.y), dz = (float)(zj - I.z);
+    const float dvx = vxj - I.vx, dvy = vyj - I.vy, dvz = vzj - I.vz;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    if (MASK) ri = self ? 0.0f : ri;
+    const float mr = mj * ri;
+    const float ri2 = ri * ri;
+    const float mr3 = mr * ri2;
+    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+    const float b3 = (rv * ri2) * 3.0f;
+    S.pp += mr;
+    S.ax = fmaf(mr3, dx, S.ax);
+    S.ay = fmaf(mr3, dy, S.ay);
+    S.az = fmaf(mr3, dz, S.az);
+    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
+    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
+    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+}
+
+// Flush of the paper-faithful mode: acceleration and potential runs go to
+// the FP64 sums, the jerk stays in its FP32 accumulator (never flushed).
+__device__ __forceinline__ void flush_keep_jerk(SumF& f, SumD& d)
+{
+    d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
+    d.pp += (double)f.pp;
+    f.ax = f.ay = f.az = f.pp = 0.0f;
+}
+
 __device__ __forceinline__ void flush(SumF& f, SumD& d)
 {
     d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
@@ -249,6 +293,12 @@ struct Tile {
 struct TileS {
     float c[12][kTJ];
     float m[kTJ];
+};
+
+// LDS tile for the paper-faithful mode: FP64 positions, FP32 velocities.
+struct TileSP {
+    double x[kTJ], y[kTJ], z[kTJ];
+    float vx[kTJ], vy[kTJ], vz[kTJ], m[kTJ];
 };
 
 // ---- tile loops ---------------------------------------------------------
@@ -346,6 +396,30 @@ __device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int
     }
 }
 
+template <bool MASK, int IPL>
+__device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L, int64_t tb,
+                                        const int (&ii)[IPL], const I64SP (&I)[IPL],
+                                        float eps2f, SumF (&f)[IPL], SumD (&S)[IPL])
+{
+    constexpr int kUnroll = IPL == 1 ? 4 : 2;
+    const int step = kMixedK * L;
+    for (int jb = 0; jb < cnt; jb += step) {
+        const int je = (jb + step < cnt) ? jb + step : cnt;
+#pragma unroll kUnroll
+        for (int jj = jb + sub; jj < je; jj += L) {
+            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+            const float vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj], mj = T.m[jj];
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
+                pair_sp<MASK>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, mj, self, f[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) flush_keep_jerk(f[q], S[q]);
+    }
+}
+
 __device__ __forceinline__ double shfl_sum(double v, int L)
 {
     for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
@@ -391,6 +465,11 @@ __device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int6
             const bool self = jj == (int64_t)ii[q];
             if constexpr (PREC == 0) {
                 pair_f64<true>(I[q], eps2, xj, yj, zj, vxj, vyj, vzj, mj, self, S[q]);
+            } else if constexpr (PREC == 3) {
+                I64SP Is{I[q].x, I[q].y, I[q].z, (float)I[q].vx, (float)I[q].vy,
+                         (float)I[q].vz};
+                pair_sp<true>(Is, eps2f, xj, yj, zj, (float)vxj, (float)vyj, (float)vzj,
+                              (float)mj, self, F[q]);
             } else {
                 pair_mixed<true>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, (float)mj, self,
                                  F[q]);
@@ -400,13 +479,19 @@ __device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int6
             if (++run == kMixedK) {
                 run = 0;
 #pragma unroll
-                for (int q = 0; q < IPL; ++q) flush(F[q], S[q]);
+                for (int q = 0; q < IPL; ++q) {
+                    if constexpr (PREC == 3) flush_keep_jerk(F[q], S[q]);
+                    else flush(F[q], S[q]);
+                }
             }
         }
     }
     if constexpr (PREC != 0) {
 #pragma unroll
-        for (int q = 0; q < IPL; ++q) flush(F[q], S[q]);
+        for (int q = 0; q < IPL; ++q) {
+            if constexpr (PREC == 3) flush_keep_jerk(F[q], S[q]);
+            else flush(F[q], S[q]);
+        }
     }
 }
 
@@ -420,10 +505,11 @@ __device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int6
 template <int PREC, bool POT_ONLY, int IPL, bool SPLIT>
 __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
 {
-    static_assert(!SPLIT || (PREC != 0 && !POT_ONLY), "split form is mixed-only");
+    static_assert(!SPLIT || (PREC == 1 || PREC == 2), "split form is for the mixed modes");
     using MT = typename std::conditional<PREC == 0, double, float>::type;
     using RUN = typename std::conditional<PREC == 2, Sum2F, SumD>::type;
-    using TT = typename std::conditional<SPLIT, TileS, Tile<MT>>::type;
+    using TT = typename std::conditional<
+        SPLIT, TileS, typename std::conditional<PREC == 3, TileSP, Tile<MT>>::type>::type;
     __shared__ TT T;
     __shared__ int32_t s_item;
 
@@ -467,6 +553,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         int pp[IPL], ii[IPL];
         I64 I[IPL];
         I32S IS[IPL];
+        I64SP ISP[IPL];
         RUN S[IPL];
         SumF F[IPL];
 #pragma unroll
@@ -479,6 +566,10 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             fetch_particle(a, ii[q], Tpred, r, w);
             I[q].x = r[0]; I[q].y = r[1]; I[q].z = r[2];
             I[q].vx = w[0]; I[q].vy = w[1]; I[q].vz = w[2];
+            if constexpr (PREC == 3) {
+                ISP[q] = I64SP{I[q].x, I[q].y, I[q].z, (float)I[q].vx, (float)I[q].vy,
+                               (float)I[q].vz};
+            }
             if constexpr (SPLIT) {
                 split(I[q].x, IS[q].xh, IS[q].xl);
                 split(I[q].y, IS[q].yh, IS[q].yl);
@@ -521,7 +612,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                         T.x[tid] = r[0];
                         T.y[tid] = r[1];
                         T.z[tid] = r[2];
-                        T.vx[tid] = w[0];
+                        T.vx[tid] = w[0];   // rounded to FP32 in the paper-faithful mode
                         T.vy[tid] = w[1];
                         T.vz[tid] = w[2];
                         T.m[tid] = (MT)a.m[jg];
@@ -543,6 +634,9 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             } else if constexpr (SPLIT) {
                 if (need_mask) tile_split<true, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
                 else           tile_split<false, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
+            } else if constexpr (PREC == 3) {
+                if (need_mask) tile_sp<true, IPL>(T, cnt, sub, L, tb, ii, ISP, eps2f, F, S);
+                else           tile_sp<false, IPL>(T, cnt, sub, L, tb, ii, ISP, eps2f, F, S);
             } else {
                 if (need_mask) tile_mixed<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
                 else           tile_mixed<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
@@ -553,6 +647,12 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         for (int q = 0; q < IPL; ++q) {
             double out[7];
             finalize(S[q], out);
+            if constexpr (PREC == 3) {
+                // the jerk was summed in FP32 over the whole j-chunk
+                out[3] = (double)F[q].jx;
+                out[4] = (double)F[q].jy;
+                out[5] = (double)F[q].jz;
+            }
             if (L > 1) {
 #pragma unroll
                 for (int r = 0; r < 7; ++r) out[r] = shfl_sum(out[r], L);
@@ -621,7 +721,7 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
 typedef void (*SweepFn)(SweepArgs);
 
 // variant: bit 0 -> two active particles per lane; bit 1 -> split
-// differences (mixed precisions only; FP64 ignores it).
+// differences (MIXED and MIXED_2F only; FP64 and MIXED_SP ignore it).
 SweepFn sweep_fn(int precision, int variant, bool pot_only)
 {
     if (pot_only) return sweep_kernel<0, true, 1, false>;
@@ -633,6 +733,8 @@ SweepFn sweep_fn(int precision, int variant, bool pot_only)
         if (spl) return two ? sweep_kernel<1, false, 2, true> : sweep_kernel<1, false, 1, true>;
         return two ? sweep_kernel<1, false, 2, false> : sweep_kernel<1, false, 1, false>;
     }
+    if (precision == 3)
+        return two ? sweep_kernel<3, false, 2, false> : sweep_kernel<3, false, 1, false>;
     if (spl) return two ? sweep_kernel<2, false, 2, true> : sweep_kernel<2, false, 1, true>;
     return two ? sweep_kernel<2, false, 2, false> : sweep_kernel<2, false, 1, false>;
 }

@@ -28,9 +28,9 @@ if not os.path.exists(LIB_PATH):
 lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENODEV, EHIP, ENOMEM, ENONFINITE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-FP64, MIXED, MIXED_2F = 0, 1, 2
+FP64, MIXED, MIXED_2F, MIXED_SP = 0, 1, 2, 3
 DT_PAPER, DT_AARSETH = 0, 1
-PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed2f": MIXED_2F}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed2f": MIXED_2F, "mixed_sp": MIXED_SP}
 INT64_MAX = (1 << 63) - 1
 
 _P = ctypes.c_void_p
@@ -47,7 +47,7 @@ class CState(ctypes.Structure):
 
 class CDtParams(ctypes.Structure):
     _fields_ = [("eta", _d), ("form", _i32), ("k_min", _i32), ("k_max", _i32),
-                ("reserved0", _i32)]
+                ("reserved0", _i32), ("eta_init", _d)]
 
 
 class CClusters(ctypes.Structure):
@@ -188,8 +188,9 @@ class Clusters:
         return c
 
 
-def dt_params(eta=0.02, form=DT_PAPER, k_min=3, k_max=20):
-    return CDtParams(float(eta), int(form), int(k_min), int(k_max), 0)
+def dt_params(eta=0.02, form=DT_PAPER, k_min=3, k_max=20, eta_init=0.0):
+    """eta_init: start-up factor of init_dt (0 = the steady factor)."""
+    return CDtParams(float(eta), int(form), int(k_min), int(k_max), 0, float(eta_init))
 
 
 def _cl(clusters):

@@ -14,6 +14,16 @@ Names:
       against a serial loop over the clusters
   c5  Plummer N = 131072 with a Salpeter mass spectrum and 10 % binaries,
       eps = 1e-5, two-float accumulation, t = 0 -> 0.25
+  e1  force and jerk error of the reduced-precision sweeps against the FP64
+      sweep as N grows (Plummer, eps = 4/N, 1K .. 256K), and the full-sweep
+      time of each precision: the cost of summing the jerk in FP64 instead
+      of FP32 (Section 3.2)
+  e2  energy conservation of block runs with the jerk summed in FP64
+      (mixed) and in FP32 (mixed_sp), Plummer N = 256K, t = 0 -> 0.125
+  e3  energy error against the number of steps per crossing time, N = 1K,
+      FP64, mixed and FP32-jerk forces (the paper's Section 4 energy study)
+  e4  whole-run speed against N (Plummer N = 1K .. 16K, eps = 4/N, t = 0 -> 1,
+      FP64 and mixed): the paper's Section 5 performance sweep
 
 Every run reports wall time, block steps, interactions, interactions/s,
 GFLOPS at the paper's 60 flops per interaction (Section 5), clamped steps
@@ -24,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import sys
 import time
 
@@ -215,7 +226,132 @@ def c5(ctx, t_end=0.25):
             "run": block_run(ctx, s, eps2, p, t_end, H.MIXED_2F, label="c5")}
 
 
-RUNNERS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+def e3(ctx, t_end=0.375, etas=(0.0025, 0.005, 0.01, 0.02, 0.04, 0.08), n=1024, seed=1):
+    """Energy error against steps per crossing time (Section 4 energy study):
+    Plummer N = 1K, eps = 4/N, mixed and FP64 forces, several eta; the
+    error is averaged over the sync times 1/8, 2/8, 3/8 (potential energy
+    from FP64 sweeps); start-up factor eta/16.  n_step = particle steps per
+    particle per crossing time (2 sqrt 2 in N-body units)."""
+    x, v, m = inputs.plummer(n, seed)
+    eps2 = (4.0 / n) ** 2
+    rows = []
+    for prec_name in ("fp64", "mixed", "mixed_sp"):
+        prec = H.PRECISIONS[prec_name]
+        for eta in etas:
+            s = H.State(x, v, m, TB)
+            # start-up factor eta/16: with the steady factor the first step
+            # dominates the error over 3/8 time units (the scheme's error,
+            # not the start-up, is what the study measures)
+            p = H.dt_params(eta, H.DT_PAPER, K_MIN, K_MAX, eta_init=eta / 16)
+            ctx.initialize(s, eps2, p, prec)
+            e0 = _energy(ctx, s, eps2)[0]
+            errs, inter, steps = [], 0, 0
+            t0 = time.perf_counter()
+            nsync = int(round(t_end * 8))
+            for k in range(1, nsync + 1):
+                st, it = ctx.run(s, eps2, p, k << (TB - 3), prec, use_graph=True,
+                                 sync_every=256)
+                steps += st
+                inter += it
+                errs.append(abs((_energy(ctx, s, eps2)[0] - e0) / e0))
+            wall = time.perf_counter() - t0
+            n_step = inter / n / n * (2.0 * math.sqrt(2.0) / t_end)
+            # final step levels: count of particles with dt = 2^-k, k = 0..TB
+            lv = TB - np.log2(s.dt.cpu().numpy()).astype(np.int64)
+            levels = np.bincount(lv, minlength=TB + 1).tolist()
+            rows.append({"precision": prec_name, "eta": eta, "n_step": n_step,
+                         "mean_rel_energy_error": float(np.mean(errs)),
+                         "rel_energy_error_at_sync": [float(e) for e in errs],
+                         "block_steps": steps, "wall_s": wall, "dt_levels_final": levels})
+            _log("  e3 %-5s eta %.3f  n_step %8.1f  <|dE/E|> %.3e" %
+                 (prec_name, eta, n_step, np.mean(errs)))
+    # slope of log error vs log n_step for FP64 over the converging part
+    # (errors in [1e-13, 1e-6): larger ones leave the asymptotic regime,
+    # smaller ones reach the FP64 rounding floor)
+    f = [r for r in rows if r["precision"] == "fp64"
+         and 1e-13 <= r["mean_rel_energy_error"] < 1e-6]
+    ln = np.log([r["n_step"] for r in f])
+    le = np.log([r["mean_rel_energy_error"] for r in f])
+    slope = float(np.polyfit(ln, le, 1)[0]) if len(f) > 1 else None
+    return {"config": "energy_vs_nstep_plummer_n%d" % n, "t_end": t_end, "rows": rows,
+            "fp64_loglog_slope": slope}
+
+
+def e1(ctx, ns=(1024, 4096, 16384, 65536, 262144), sample=4096, seed=5):
+    """Accuracy and cost of the precision modes against N (Section 3.2).
+
+    For each N: a sample of up to `sample` particles evenly spread over the
+    index range; per-particle relative errors |f - f64| / |f64| of the
+    acceleration and the jerk of each reduced-precision sweep against the
+    FP64 sweep (median, 99th percentile, max), and the full-sweep time
+    (n_act = N) of every precision."""
+    rows = []
+    for n in ns:
+        x, v, m = inputs.plummer(n, seed)
+        s = H.State(x, v, m, TB)
+        s.xp.copy_(s.x)     # the sweep reads the predicted arrays
+        s.vp.copy_(s.v)
+        eps2 = (4.0 / n) ** 2
+        k = min(sample, n)
+        idx = torch.from_numpy((np.arange(k, dtype=np.int64) * n // k).astype(np.int32)).cuda()
+        ref_a, ref_j, _ = ctx.force_jerk(s, idx, eps2, H.FP64)
+        ref_a, ref_j = ref_a.cpu().numpy(), ref_j.cpu().numpy()
+        row = {"n": n, "sample": k, "errors": {}, "sweep_ms": {}}
+        for pname in ("mixed", "mixed2f", "mixed_sp"):
+            a, j, _ = ctx.force_jerk(s, idx, eps2, H.PRECISIONS[pname])
+            a, j = a.cpu().numpy(), j.cpu().numpy()
+            ea = np.linalg.norm(a - ref_a, axis=0) / np.linalg.norm(ref_a, axis=0)
+            ej = np.linalg.norm(j - ref_j, axis=0) / np.linalg.norm(ref_j, axis=0)
+            row["errors"][pname] = {
+                "acc": [float(np.median(ea)), float(np.percentile(ea, 99)), float(ea.max())],
+                "jerk": [float(np.median(ej)), float(np.percentile(ej, 99)), float(ej.max())]}
+        reps = max(2, min(50, int(4e10 / (n * n))))
+        for pname in ("fp64", "mixed", "mixed2f", "mixed_sp"):
+            ms = sweep_time(ctx, s, eps2, H.PRECISIONS[pname], reps=reps)
+            row["sweep_ms"][pname] = ms
+        rows.append(row)
+        _log("  e1 N %7d  jerk rel err median mixed %.2e  mixed_sp %.2e  "
+             "sweep ms fp64 %.3f mixed %.3f mixed_sp %.3f"
+             % (n, row["errors"]["mixed"]["jerk"][0], row["errors"]["mixed_sp"]["jerk"][0],
+                row["sweep_ms"]["fp64"], row["sweep_ms"]["mixed"], row["sweep_ms"]["mixed_sp"]))
+    return {"config": "precision_vs_n_plummer", "error_stats": "median, p99, max", "rows": rows}
+
+
+def e2(ctx, t_end=0.125, n=262144, seed=6):
+    """Block runs with FP64 (mixed) and FP32 (mixed_sp) jerk sums side by
+    side: the paper finds no difference in energy conservation (Section 4)."""
+    x, v, m = inputs.plummer(n, seed)
+    eps2 = (4.0 / n) ** 2
+    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    out = {"config": "plummer_n%d_jerk_sum_precision" % n, "t_end": t_end, "runs": {}}
+    for pname in ("mixed", "mixed_sp"):
+        s = H.State(x, v, m, TB)
+        ctx.initialize(s, eps2, p, H.PRECISIONS[pname])
+        out["runs"][pname] = block_run(ctx, s, eps2, p, t_end, H.PRECISIONS[pname],
+                                       label="e2 " + pname)
+    return out
+
+
+def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7):
+    """Whole-run interactions/s and GFLOPS (60 flops per interaction)
+    against N, from t = 0 to t_end (Section 5, Fig. of GFLOPS vs N)."""
+    rows = []
+    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    for n in ns:
+        x, v, m = inputs.plummer(n, seed)
+        eps2 = (4.0 / n) ** 2
+        for pname in ("fp64", "mixed"):
+            s = H.State(x, v, m, TB)
+            ctx.initialize(s, eps2, p, H.PRECISIONS[pname])
+            r = block_run(ctx, s, eps2, p, t_end, H.PRECISIONS[pname],
+                          label="e4 n%d %s" % (n, pname))
+            r.update({"n": n, "precision": pname})
+            rows.append(r)
+    return {"config": "plummer_speed_vs_n", "t_end": t_end, "rows": rows}
+
+
+RUNNERS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "e1": e1, "e2": e2, "e3": e3,
+           "e4": e4}
 
 
 def main(argv=None):

@@ -63,3 +63,30 @@ def test_binding_names_match_header():
         if n == "hermite_last_error":
             continue
         assert n in herm._SIGS, n
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the C layout of include/hermite.h
+    (size and every field offset, as the host C compiler lays them out)."""
+    import subprocess
+    from paper_1104_2700_amd import hermite as H
+    structs = {"hermite_state": H.CState, "hermite_dt_params": H.CDtParams,
+               "hermite_clusters": H.CClusters, "hermite_tuning": H.CTuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hermite.h"',
+             'int main(void) {']
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

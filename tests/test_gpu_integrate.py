@@ -139,23 +139,27 @@ def _c1_setup(H, n=1024, seed=1, eps=1.0 / 64):
     return x, v, m, eps * eps
 
 
-def test_initialize_and_energy(H, ctx):
+@pytest.mark.parametrize("form,eta_init", [(0, 0.0), (1, 0.0), (0, 0.05)])
+def test_initialize_and_energy(H, ctx, form, eta_init):
     from oracle import oracle as O
     x, v, m, eps2 = _c1_setup(H)
     n = m.shape[0]
-    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    eta = 0.02
+    params = H.dt_params(eta, form, 3, 20, eta_init=eta_init)
     s = H.State(x, v, m, TB)
     ctx.initialize(s, eps2, params, H.FP64)
     e = ctx.energy(s, eps2)
     torch.cuda.synchronize()
     ost = O.new_state(x, v, m, TB)
-    O.initialize(ost, eps2, 0.02, 0, 3, 20)
+    O.initialize(ost, eps2, eta, form, 3, 20, eta_init=eta_init)
     g = s.to_numpy()
     _, _, _, cond = O.force(x, v, m, np.arange(n, dtype=np.int32), eps2, with_cond=True)
     check_fp64("a0", g["a"], ost["a"], cond[0], n)
     check_fp64("j0", g["j"], ost["j"], cond[1], n)
     assert np.all(g["t"] == 0)
-    crit = 0.02 * np.linalg.norm(ost["a"], axis=0) / np.linalg.norm(ost["j"], axis=0)
+    # start-up factor (written out here only to locate quantisation ties)
+    eta_s = eta_init if eta_init > 0 else (eta if form == 0 else np.sqrt(eta))
+    crit = eta_s * np.linalg.norm(ost["a"], axis=0) / np.linalg.norm(ost["j"], axis=0)
     mism = g["dt"] != ost["dt"]
     assert np.all(_near_boundary(crit[mism], 1e-9))
     K, W = O.energy(x, v, m, eps2)

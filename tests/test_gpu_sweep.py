@@ -64,13 +64,13 @@ def test_fp64_sweep_parity(H, ctx, n, n_act):
 def variant(H, ctx, request):
     """Installs launch-shape variant `request.param` for every precision
     (bit 0: two particles per lane, bit 1: split FP32 differences)."""
-    saved = [ctx.get_tuning(p) for p in range(3)]
-    for p in range(3):
+    saved = [ctx.get_tuning(p) for p in range(4)]
+    for p in range(4):
         t = ctx.get_tuning(p)
         t.variant = request.param
         ctx.set_tuning(p, t)
     yield request.param
-    for p in range(3):
+    for p in range(4):
         ctx.set_tuning(p, saved[p])
 
 
@@ -104,6 +104,27 @@ def test_mixed_sweep_parity(H, ctx, variant, prec, n, n_act):
     check_mixed("acc", acc.cpu().numpy(), ra, cond[0])
     check_mixed("jerk", jrk.cpu().numpy(), rj, cond[1])
     check_mixed("pot", pot.cpu().numpy()[None], rp[None], cond[2])
+
+
+@pytest.mark.parametrize("variant", [0, 1], indirect=True)
+@pytest.mark.parametrize("n,n_act", [(1, 1), (64, 7), (257, 257), (1024, 1024),
+                                     (4097, 65), (5000, 1)])
+def test_mixed_sp_sweep_parity(H, ctx, variant, n, n_act):
+    """FP32-velocity / FP32-jerk mode (Section 3.2 as printed).  Acc and pot
+    meet the mixed bar.  The jerk is one FP32 running sum per lane over up
+    to n terms, so its rounding-order bound is the recursive-summation one,
+    (16 + n) u32 sum_j |term_j|; the FP32 rounding of the velocities adds
+    <= u32 (|v_i| + |v_j|) per term, inside the 16."""
+    from oracle import oracle as O
+    s, x, v, m = _state(H, n, 400 + n)
+    eps2 = (4.0 / max(n, 64)) ** 2
+    idx = _idx(n, n_act, n + 13)
+    acc, jrk, pot = ctx.force_jerk(s, torch.from_numpy(idx).cuda(), eps2, H.MIXED_SP)
+    torch.cuda.synchronize()
+    ra, rj, rp, cond = O.force(x, v, m, idx, eps2, with_cond=True)
+    check_mixed("acc", acc.cpu().numpy(), ra, cond[0])
+    check_mixed("pot", pot.cpu().numpy()[None], rp[None], cond[2])
+    check_mixed("jerk", jrk.cpu().numpy(), rj, cond[1], tol=0.0, cond_factor=16.0 + n)
 
 
 def test_identity_index_and_device_count(H, ctx):
