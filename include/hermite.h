@@ -238,7 +238,9 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
  * a multiple of 2^(tick_bits - k_min)), or until max_steps steps have been
  * launched (max_steps <= 0: no limit; the call can then be repeated to
  * continue).  The host reads the device block time once every sync_every
- * steps.  steps_out / interactions_out (host, may be NULL) receive the
+ * steps.  With use_graph != 0, runs of 8 consecutive steps are captured as
+ * one graph (steps past T_end are no-ops), which removes the gap between
+ * graph launches that dominates small systems.  steps_out / interactions_out (host, may be NULL) receive the
  * block-step count and the number of pair interactions (sum over steps of
  * sum_i n_c(i)) of this call; done_out (host, may be NULL) is set to 1 when
  * every particle has reached T_end. */
@@ -250,12 +252,14 @@ int hermite_run(hermite_ctx* ctx, const hermite_state* s,
 
 /* Cumulative device counters since creation (synchronises `stream`):
  * out[0] block steps, out[1] interactions, out[2] clamped steps,
- * out[3] last block time T, out[4] last n_act. */
+ * out[3] block time T and out[4] n_act of the last step that had active
+ * particles. */
 int hermite_counters(hermite_ctx* ctx, int64_t out[5], void* stream);
 
 /* Histogram of the active-block sizes of every block step since creation
- * (synchronises `stream`): out[0] counts steps with n_act = 0 past T_end,
- * out[b] for b >= 1 counts steps with 2^(b-1) <= n_act < 2^b. */
+ * (synchronises `stream`): out[b] for b >= 1 counts steps with
+ * 2^(b-1) <= n_act < 2^b; out[0] stays 0 (steps past T_end are not
+ * counted anywhere). */
 int hermite_block_histogram(hermite_ctx* ctx, int64_t out[33], void* stream);
 
 /* ---- launch shape and autotuner ------------------------------------------ */

@@ -52,6 +52,10 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// Block steps per graph in hermite_run: one graph launch costs about as
+// much as a small system's whole step, so runs replay several steps each.
+constexpr int kRunGraphSteps = 8;
+
 struct GraphEntry {
     std::string key;
     hipGraph_t graph = nullptr;
@@ -545,9 +549,22 @@ int hermite_energy(hermite_ctx* c, const hermite_state* s, const hermite_cluster
     return HERMITE_OK;
 }
 
+// Enqueues K consecutive block steps; with use_graph they are captured
+// once as one graph (keyed by the step parameters and K) and replayed.
+static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                        double eps2, int precision, const hermite_dt_params* p,
+                        int64_t T_end, int use_graph, int K, void* stream);
+
 int hermite_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                  double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
                  int use_graph, void* stream)
+{
+    return launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, stream);
+}
+
+static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                        double eps2, int precision, const hermite_dt_params* p,
+                        int64_t T_end, int use_graph, int K, void* stream)
 {
     CHECK(check_ctx(c));
     CHECK(check_state(s));
@@ -565,9 +582,13 @@ int hermite_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
                             c->tuning[precision], out, out + 3 * s->n, out + 6 * s->n, &a));
     }
     hipStream_t st = (hipStream_t)stream;
-    if (!use_graph) return enqueue_step(c, s, cl, eps2, precision, p, T_end, st);
+    if (!use_graph) {
+        for (int k = 0; k < K; ++k) CHECK(enqueue_step(c, s, cl, eps2, precision, p, T_end, st));
+        return HERMITE_OK;
+    }
 
-    const std::string key = step_key(s, cl, eps2, precision, p, T_end, c->tuning[precision]);
+    const std::string key = step_key(s, cl, eps2, precision, p, T_end, c->tuning[precision]) +
+                            "|K" + std::to_string(K);
     GraphEntry* g = nullptr;
     for (auto& e : c->graphs)
         if (e.key == key) g = &e;
@@ -581,7 +602,9 @@ int hermite_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
         GraphEntry e;
         e.key = key;
         HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(c, s, cl, eps2, precision, p, T_end, c->cap_stream);
+        int rc = HERMITE_OK;
+        for (int k = 0; k < K && rc == HERMITE_OK; ++k)
+            rc = enqueue_step(c, s, cl, eps2, precision, p, T_end, c->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
         if (rc != HERMITE_OK) {
@@ -647,8 +670,12 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
     for (;;) {
         int batch = sync_every;
         if (max_steps > 0 && launched + batch > max_steps) batch = (int)(max_steps - launched);
-        for (int k = 0; k < batch; ++k)
-            CHECK(hermite_step(c, s, cl, eps2, precision, p, T_end, use_graph, stream));
+        int k = 0;
+        for (; k + kRunGraphSteps <= batch; k += kRunGraphSteps)
+            CHECK(launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, kRunGraphSteps,
+                               stream));
+        for (; k < batch; ++k)
+            CHECK(launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, stream));
         launched += batch;
         int64_t T = 0;
         int32_t na = 0;

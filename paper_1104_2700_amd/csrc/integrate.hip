@@ -217,14 +217,18 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
     return off + block_total;
 }
 
+// Counts a block step.  A step with no active particle is one past T_end
+// (every live step has at least one): it leaves the counters untouched, so
+// replaying extra steps after the end changes nothing.
 __device__ void count_step(int64_t* counters, int64_t T, int32_t na)
 {
-    if (counters) {
-        counters[0] += na > 0 ? 1 : 0;
+    if (counters && na > 0) {
+        // non-returning atomics: the caller does not wait for the update
+        atomicAdd((unsigned long long*)&counters[0], 1ull);
         counters[3] = T;
         counters[4] = na;
-        const int bin = na > 0 ? 32 - __clz(na) : 0;   // block-size histogram
-        counters[kHistBase + bin] += 1;
+        const int bin = 32 - __clz(na);                 // block-size histogram
+        atomicAdd((unsigned long long*)&counters[kHistBase + bin], 1ull);
     }
 }
 
@@ -282,6 +286,70 @@ __global__ void __launch_bounds__(kWG) sel_write_plan_kernel(
     }
     __syncthreads();
     plan_body(sa, s_na);
+}
+
+// Stages 1-3 and the sweep plan in one workgroup, for systems that fit one
+// selection block (n <= kSelBlock): no cross-block ticket or fence, one
+// launch instead of two.  Each thread owns kSelPer consecutive particles,
+// so a scan over threads writes the active list in ascending order.
+__global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
+    int64_t n, const int64_t* t, const int64_t* dt, int64_t T_end, int32_t* idx,
+    int32_t* n_act, int64_t* T_out, int64_t* counters, SweepArgs sa)
+{
+    constexpr int kWaves = kWG / 64;
+    __shared__ int64_t s_min[kWaves];
+    __shared__ int32_t s_cnt[kWaves];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t base = (int64_t)tid * kSelPer;
+    int64_t e[kSelPer];
+    int64_t v = INT64_MAX;
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + r;
+        e[r] = i < n ? t[i] + dt[i] : INT64_MAX;
+        v = e[r] < v ? e[r] : v;
+    }
+    // block minimum: wave butterfly, then the kWaves wave minima
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    if (lane == 0) s_min[wave] = v;
+    __syncthreads();
+    int64_t T = s_min[0];
+    for (int w = 1; w < kWaves; ++w) T = s_min[w] < T ? s_min[w] : T;
+    const bool live = T <= T_end;
+    int32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r) c += (e[r] == T) ? 1 : 0;
+    // ascending positions: inclusive wave scan, then the wave offsets
+    int32_t x = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    if (lane == 63) s_cnt[wave] = x;
+    __syncthreads();
+    int32_t off = 0, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        off += w < wave ? s_cnt[w] : 0;
+        total += s_cnt[w];
+    }
+    if (live) {
+        int32_t pos = off + x - c;
+#pragma unroll
+        for (int r = 0; r < kSelPer; ++r)
+            if (e[r] == T) idx[pos++] = (int32_t)(base + r);
+    }
+    const int32_t na = live ? total : 0;
+    if (tid == 0) {
+        *T_out = T;
+        *n_act = na;
+        count_step(counters, T, na);
+    }
+    plan_body(sa, na);
 }
 
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
@@ -544,6 +612,11 @@ hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, in
                               const SweepArgs& sa, hipStream_t st)
 {
     const int nb = nblocks(n, kSelBlock);
+    if (nb == 1) {
+        hipLaunchKernelGGL(sel_single_plan_kernel, dim3(1), dim3(kWG), 0, st, n, t, dt, T_end,
+                           idx, n_act, T, counters, sa);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(sel_min_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min,
                        block_cnt, nb, T, ticket + 1);
     hipLaunchKernelGGL(sel_write_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,

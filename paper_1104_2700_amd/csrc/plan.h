@@ -44,6 +44,47 @@ __device__ inline int lower_bound_idx(const int32_t* a, int count, int64_t key)
 // list of (cluster, i-tile, j-chunk) items, and adds the sweep's
 // interaction count to the counters.
 // ------------------------------------------------------------------------
+// The split for na active particles of (at most) c_act active clusters:
+// lanes per particle L, particles per item ti, chunk length jc.
+__device__ inline void plan_split(const SweepArgs& a, int32_t na, int64_t c_act, int32_t* L_out,
+                                  int32_t* ti_out, int64_t* jc_out)
+{
+    const int C = a.n_clusters;
+    // Work items wanted (about one per resident workgroup slot, times the
+    // tuning factor), and the most j-chunks a cluster can give (each chunk
+    // at least one LDS tile, all partial sums in the buffer).
+    const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
+    int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
+    if (na > 0) {
+        const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
+        if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
+    }
+    // Fewest lanes per particle that (a) still yields enough items and
+    // (b) keeps tiles at least half full given the active particles per
+    // active cluster: more particles per item means more work per staged j
+    // tile, but a tile larger than a cluster's active run leaves lanes idle.
+    const int64_t per_cluster = (na + c_act - 1) / c_act;
+    int32_t L = 1;
+    for (; L < 64; L <<= 1) {
+        const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+        const int64_t tiles = (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0);
+        if (tiles * s_cap >= want && ti_l <= 2 * per_cluster) break;
+    }
+    const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
+    const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0) : 1;
+    int64_t S = (want + tiles - 1) / tiles;
+    if (S > s_cap) S = s_cap;
+    if (S < 1) S = 1;
+    int64_t jc = (a.n_cmax + S - 1) / S;
+    const int64_t jmin = (int64_t)L * a.min_j_per_lane;
+    if (jc < jmin) jc = jmin;
+    jc = (jc + kTJ - 1) / kTJ * kTJ;
+    // rounding jc up can only lower the chunk count, so the buffer fits
+    *L_out = L;
+    *ti_out = (int32_t)ti_l;
+    *jc_out = jc;
+}
+
 __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
 {
     __shared__ int32_t s_items[kWG];
@@ -54,6 +95,33 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
     const int tid = threadIdx.x;
     const int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
     const int C = a.n_clusters;
+    if (C == 1) {
+        // one system: everything follows from na and n, no scans needed
+        if (tid == 0) {
+            int32_t L, ti;
+            int64_t jc;
+            plan_split(a, na, 1, &L, &ti, &jc);
+            const int32_t tiles = (na + ti - 1) / ti;
+            const int32_t ch = na > 0 ? (int32_t)((a.n + jc - 1) / jc) : 0;
+            a.act_start[0] = 0;
+            a.act_cnt[0] = na;
+            a.chunks[0] = ch;
+            a.item_off[0] = 0;
+            a.item_off[1] = tiles * ch;
+            SweepPlan* P = a.plan;
+            P->n_act = na;
+            P->L = L;
+            P->ti = ti;
+            P->s_max = ch;
+            P->jc = jc;
+            P->total_items = tiles * ch;
+            P->next_item = 0u;
+            if (a.counters && na > 0)
+                atomicAdd((unsigned long long*)&a.counters[1],
+                          (unsigned long long)((int64_t)na * a.n));
+        }
+        return;
+    }
     const int per = (C + kWG - 1) / kWG;
     const int c0 = tid * per;
     const int c1 = (c0 + per < C) ? c0 + per : C;
@@ -87,39 +155,10 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
 
     // 2. the split: lanes per particle L and chunk length jc
     if (tid == 0) {
-        const int64_t c_act = s_items[0] > 0 ? s_items[0] : 1;
-        // Work items wanted (about one per resident workgroup slot, times
-        // the tuning factor), and the most j-chunks a cluster can give
-        // (each chunk at least one LDS tile, all partial sums in the buffer).
-        const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
-        int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
-        if (na > 0) {
-            const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
-            if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
-        }
-        // Fewest lanes per particle that (a) still yields enough items and
-        // (b) keeps tiles at least half full given the active particles
-        // per active cluster: more particles per item means more work per
-        // staged j tile, but a tile larger than a cluster's active run
-        // leaves lanes idle.
-        const int64_t per_cluster = (na + c_act - 1) / c_act;
-        int32_t L = 1;
-        for (; L < 64; L <<= 1) {
-            const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-            const int64_t tiles = (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0);
-            if (tiles * s_cap >= want && ti_l <= 2 * per_cluster) break;
-        }
-        const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-        const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0) : 1;
-        int64_t S = (want + tiles - 1) / tiles;
-        if (S > s_cap) S = s_cap;
-        if (S < 1) S = 1;
-        int64_t jc = (a.n_cmax + S - 1) / S;
-        const int64_t jmin = (int64_t)L * a.min_j_per_lane;
-        if (jc < jmin) jc = jmin;
-        jc = (jc + kTJ - 1) / kTJ * kTJ;
-        // rounding jc up can only lower the chunk count, so the buffer fits
-        s_L = L; s_ti = (int32_t)ti_l; s_jc = jc;
+        int32_t L, ti_l;
+        int64_t jc;
+        plan_split(a, na, s_items[0] > 0 ? s_items[0] : 1, &L, &ti_l, &jc);
+        s_L = L; s_ti = ti_l; s_jc = jc;
     }
     __syncthreads();
     const int32_t ti = s_ti;
@@ -170,9 +209,9 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         P->jc = jc;
         P->total_items = s_items[kWG - 1];
         P->next_item = 0u;
-        if (a.counters) {
-            a.counters[1] += s_inter[kWG - 1];
-        }
+        if (a.counters && s_inter[kWG - 1] > 0)
+            atomicAdd((unsigned long long*)&a.counters[1],
+                      (unsigned long long)s_inter[kWG - 1]);
     }
 }
 
@@ -187,7 +226,7 @@ __device__ inline int cluster_of(const SweepArgs& a, int p)
 // out = acc xyz, jerk xyz, pot.  One thread per particle.
 __device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[7])
 {
-    const int ch = a.chunks[cluster_of(a, p)];
+    const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
 #pragma unroll
     for (int q = 0; q < 7; ++q) out[q] = 0.0;
     for (int k = 0; k < ch; ++k) {
@@ -202,7 +241,7 @@ __device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double
 __device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, int lane,
                                             double out[7])
 {
-    const int ch = a.chunks[cluster_of(a, p)];
+    const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
 #pragma unroll
     for (int q = 0; q < 7; ++q) out[q] = 0.0;
     for (int k = lane; k < ch; k += 64) {

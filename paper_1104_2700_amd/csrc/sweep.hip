@@ -46,6 +46,7 @@ namespace hm {
 namespace {
 
 constexpr int kMixedK = 16;   // FP32 run length before an FP64 flush
+constexpr int64_t kDirectMinJ = 1024;   // shortest j-chunk read without LDS
 
 __device__ __forceinline__ double rsqrt_f64(double s)
 {
@@ -534,13 +535,14 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     for (;; ) {
         if (item >= total) break;
 
+        // one system: the item layout follows from the plan alone
         const int c = (C == 1) ? 0 : upper_bound_i32(a.item_off, C + 1, item) - 1;
-        const int local = item - a.item_off[c];
-        const int ch = a.chunks[c];
+        const int local = (C == 1) ? item : item - a.item_off[c];
+        const int ch = (C == 1) ? P->s_max : a.chunks[c];
         const int tile_i = local / ch;
         const int k = local - tile_i * ch;
-        const int p0 = a.act_start[c] + tile_i * ti;
-        const int rem = a.act_cnt[c] - tile_i * ti;
+        const int p0 = ((C == 1) ? 0 : a.act_start[c]) + tile_i * ti;
+        const int rem = ((C == 1) ? na : a.act_cnt[c]) - tile_i * ti;
         const int pcnt = rem < ti ? rem : ti;
         const int64_t cb = (C == 1) ? 0 : a.offsets[c];
         const int64_t ce = (C == 1) ? n : a.offsets[c + 1];
@@ -582,13 +584,18 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             F[q].zero();
         }
 
+        // A whole wave per particle and a long chunk: lanes read consecutive
+        // j straight from global memory (no LDS, no barrier).  Short chunks
+        // go through LDS, where one cooperative tile load replaces a round
+        // trip per j and lane.
+        const bool direct = !POT_ONLY && L == 64 && jc >= kDirectMinJ;
         if constexpr (!POT_ONLY) {
-            if (L == 64) {
+            if (direct) {
                 // wave-uniform: every lane of the wave serves the same particles
                 direct_loop<PREC, IPL>(a, j0, j1, sub, ii, I, eps2, F, S);
             }
         }
-        for (int64_t tb = j0; tb < j1 && (POT_ONLY || L < 64); tb += kTJ) {
+        for (int64_t tb = j0; tb < j1 && !direct; tb += kTJ) {
             const int cnt = (int)((j1 - tb) < kTJ ? (j1 - tb) : kTJ);
             __syncthreads();
             if (tid < cnt) {

@@ -45,6 +45,7 @@ from . import hermite as H
 from . import inputs
 
 TB = 20          # time tick 2^-20
+FORMS = {"paper": H.DT_PAPER, "aarseth": H.DT_AARSETH}
 K_MIN, K_MAX = 3, 20
 
 
@@ -332,11 +333,12 @@ def e2(ctx, t_end=0.125, n=262144, seed=6):
     return out
 
 
-def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7):
+def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7, form="paper"):
     """Whole-run interactions/s and GFLOPS (60 flops per interaction)
-    against N, from t = 0 to t_end (Section 5, Fig. of GFLOPS vs N)."""
+    against N, from t = 0 to t_end (Section 5, Fig. of GFLOPS vs N); eta =
+    0.02 in the printed form eta sqrt(R) or the classic sqrt(eta R)."""
     rows = []
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = H.dt_params(0.02, FORMS[form], K_MIN, K_MAX)
     for n in ns:
         x, v, m = inputs.plummer(n, seed)
         eps2 = (4.0 / n) ** 2
@@ -347,7 +349,7 @@ def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7):
                           label="e4 n%d %s" % (n, pname))
             r.update({"n": n, "precision": pname})
             rows.append(r)
-    return {"config": "plummer_speed_vs_n", "t_end": t_end, "rows": rows}
+    return {"config": "plummer_speed_vs_n", "t_end": t_end, "dt_form": form, "rows": rows}
 
 
 RUNNERS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "e1": e1, "e2": e2, "e3": e3,
@@ -360,6 +362,8 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=None)
     ap.add_argument("--serial-t-end", type=float, default=None)
     ap.add_argument("--serial-clusters", type=int, default=None)
+    ap.add_argument("--form", choices=sorted(FORMS), default=None,
+                    help="timestep criterion form (e4 only)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     ctx = H.Context(0)
@@ -370,6 +374,8 @@ def main(argv=None):
         kw["serial_t_end"] = a.serial_t_end
     if a.name == "c4" and a.serial_clusters is not None:
         kw["serial_clusters"] = a.serial_clusters
+    if a.name == "e4" and a.form is not None:
+        kw["form"] = a.form
     _log("workload %s %s" % (a.name, kw))
     res = RUNNERS[a.name](ctx, **kw)
     res["device"] = torch.cuda.get_device_name(0)
