@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
 {
     const int na = sa.plan->n_act;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
-    if (sa.plan->s_max <= kWaveReduceChunks) {
+    if (thread_reduce(sa.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
             double s[7];
             reduce_partials(sa, na, p, s);

@@ -278,7 +278,16 @@ __device__ inline void fetch_particle(const SweepArgs& a, int64_t i, int64_t T, 
     }
 }
 
-// Chunk counts above this use the wave-per-particle reduction.
+// Chunk counts above kWaveReduceChunks use the wave-per-particle
+// reduction, unless the active block is large enough that one thread per
+// particle already fills the chip: then the thread form, whose loads are
+// coalesced over particles, is the faster one.
 constexpr int kWaveReduceChunks = 16;
+constexpr int kThreadReduceMinAct = 16384;
+
+__device__ __forceinline__ bool thread_reduce(int s_max, int na)
+{
+    return s_max <= kWaveReduceChunks || na >= kThreadReduceMinAct;
+}
 
 }  // namespace hm

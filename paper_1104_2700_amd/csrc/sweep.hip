@@ -708,7 +708,7 @@ template <bool POT_ONLY>
 __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
 {
     const int na = a.plan->n_act;
-    if (a.plan->s_max <= kWaveReduceChunks) {
+    if (thread_reduce(a.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
             double s[7];
             reduce_partials(a, na, p, s);
