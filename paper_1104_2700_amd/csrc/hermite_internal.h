@@ -47,6 +47,11 @@ struct SweepArgs {
     SweepPlan* plan;
     int32_t* act_start;        // [C]
     int32_t* act_cnt;          // [C]
+    // Block-step path with clusters: the selection writes act_start (for
+    // every cluster that starts below n) and the cluster of every active
+    // position, so neither the plan nor the reduction searches.
+    int32_t* act_cluster;      // [n_act_max] or null
+    int32_t sel_clusters;      // nonzero: act_start / act_cluster come from the selection
     int32_t* chunks;           // [C]
     int32_t* item_off;         // [C+1]
     double* partial;           // [s_max][7][n_act]
@@ -73,6 +78,10 @@ struct SweepArgs {
     double* jerk;              // [3][n_act_max] or null
     double* pot;               // [n_act_max] or null
 };
+
+// Cluster tables up to this many entries are staged in LDS by the kernels
+// that search them (offsets in the selection, item offsets in the sweep).
+constexpr int kLdsClusters = 2048;
 
 // Grid of the grid-stride reduce/correct kernels: enough blocks for one
 // wave per particle (the many-chunk mode), capped at 4096 blocks; the

@@ -73,7 +73,7 @@ struct hermite_ctx {
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     Buf sel_min, sel_cnt;
-    Buf step_idx, step_na, step_T, step_out, phi, counters, ticket;
+    Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket;
     std::vector<GraphEntry> graphs;
 };
 
@@ -240,6 +240,7 @@ int run_force(hermite_ctx* c, const SweepArgs& a, int precision, const hermite_t
 int ensure_step_scratch(hermite_ctx* c, int64_t n)
 {
     CHECK(ensure(c, c->step_idx, sizeof(int32_t) * n));
+    CHECK(ensure(c, c->step_acl, sizeof(int32_t) * n));
     CHECK(ensure(c, c->step_na, sizeof(int32_t) * 2));
     CHECK(ensure(c, c->step_T, sizeof(int64_t) * 2));
     CHECK(ensure(c, c->step_out, sizeof(double) * 7 * n));
@@ -271,6 +272,9 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, na, (int32_t)n, eps2, tu, out,
                         out + 3 * n, out + 6 * n, &a));
     a.ipl = (tu.variant & 1) ? 2 : 1;
+    // with clusters the selection records the active runs and clusters
+    a.act_cluster = cl ? (int32_t*)c->step_acl.p : nullptr;
+    a.sel_clusters = cl ? 1 : 0;
     // prediction happens inside the sweep and the corrector (no pass over
     // the whole state: only particles a sweep touches are predicted)
     a.pred_x = s->x;
@@ -385,7 +389,8 @@ int hermite_destroy(hermite_ctx* c)
     drop_graphs(c);
     Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
                    &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
-                   &c->step_T, &c->step_out, &c->phi, &c->counters, &c->ticket};
+                   &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
+                   &c->ticket};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -174,10 +174,52 @@ __device__ __forceinline__ void predict_one(int64_t n, int64_t i, int64_t T, con
     }
 }
 
+// Writes the active indices of elements i = base .. base+kSelPer-1 from
+// position pos on (f: which are active).  With clusters (cl_off = the C
+// cluster starts, in LDS or global memory) it also records, for every
+// cluster that starts in this range, how many active particles precede
+// that start (act_start), and the cluster of every active position
+// (act_cluster): the plan and the reduction then need no searches.
+__device__ __forceinline__ void write_active(int64_t n, int64_t base, const bool* f, int32_t pos,
+                                             int32_t* idx, const int64_t* cl_off, int C,
+                                             int32_t* act_start, int32_t* act_cluster)
+{
+    if (!cl_off) {
+        for (int r = 0; r < kSelPer; ++r)
+            if (f[r]) idx[pos++] = (int32_t)(base + r);
+        return;
+    }
+    int cn = lower_bound_i64(cl_off, C, base);   // first cluster starting at >= base
+    for (int r = 0; r < kSelPer; ++r) {
+        const int64_t i = base + r;
+        if (i >= n) break;
+        while (cn < C && cl_off[cn] == i) act_start[cn++] = pos;
+        if (f[r]) {
+            idx[pos] = (int32_t)i;
+            act_cluster[pos] = cn - 1;
+            ++pos;
+        }
+    }
+}
+
+// Stages the C cluster starts in LDS when they fit (all threads call);
+// returns the table to search.
+__device__ __forceinline__ const int64_t* stage_cluster_starts(const SweepArgs& sa, int64_t* s_off)
+{
+    if (!sa.sel_clusters || sa.n_clusters <= 1) return nullptr;
+    const int C = sa.n_clusters;
+    if (C > kLdsClusters) return sa.offsets;
+    for (int k = threadIdx.x; k < C; k += kWG) s_off[k] = sa.offsets[k];
+    __syncthreads();
+    return s_off;
+}
+
 // Writes this block's active indices; returns the block's active count.
 __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt,
                                   const int32_t* block_cnt, int64_t T, bool live,
-                                  int32_t* idx, int32_t* sh)
+                                  int32_t* idx, int32_t* sh, const int64_t* cl_off = nullptr,
+                                  int C = 1, int32_t* act_start = nullptr,
+                                  int32_t* act_cluster = nullptr)
 {
     int32_t pre = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += kWG) pre += block_cnt[b];
@@ -207,12 +249,9 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
         sh[threadIdx.x] += v;
         __syncthreads();
     }
-    int32_t pos = off + sh[threadIdx.x] - c;
+    const int32_t pos = off + sh[threadIdx.x] - c;
     const int32_t block_total = sh[kWG - 1];
-    if (live) {
-        for (int r = 0; r < kSelPer; ++r)
-            if (f[r]) idx[pos++] = (int32_t)(base + r);
-    }
+    if (live) write_active(n, base, f, pos, idx, cl_off, C, act_start, act_cluster);
     __syncthreads();
     return off + block_total;
 }
@@ -259,9 +298,12 @@ __global__ void __launch_bounds__(kWG) sel_write_plan_kernel(
     __shared__ int32_t sh[kWG];
     __shared__ int32_t s_last;
     __shared__ int32_t s_na;
+    __shared__ int64_t s_off[kLdsClusters];
+    const int64_t* cl_off = stage_cluster_starts(sa, s_off);
     const int64_t T = *T_in;
     const bool live = T <= T_end;
-    (void)sel_write_body(n, t, dt, block_cnt, T, live, idx, sh);
+    (void)sel_write_body(n, t, dt, block_cnt, T, live, idx, sh, cl_off, sa.n_clusters,
+                         sa.act_start, sa.act_cluster);
     // the last block to arrive sees every block's indices
     __threadfence();
     __syncthreads();
@@ -299,6 +341,8 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
     constexpr int kWaves = kWG / 64;
     __shared__ int64_t s_min[kWaves];
     __shared__ int32_t s_cnt[kWaves];
+    __shared__ int64_t s_off[kLdsClusters];
+    const int64_t* cl_off = stage_cluster_starts(sa, s_off);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -338,11 +382,13 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
         total += s_cnt[w];
     }
     if (live) {
-        int32_t pos = off + x - c;
+        bool f[kSelPer];
 #pragma unroll
-        for (int r = 0; r < kSelPer; ++r)
-            if (e[r] == T) idx[pos++] = (int32_t)(base + r);
+        for (int r = 0; r < kSelPer; ++r) f[r] = e[r] == T;
+        write_active(n, base, f, off + x - c, idx, cl_off, sa.n_clusters, sa.act_start,
+                     sa.act_cluster);
     }
+    __syncthreads();   // act_start complete before the plan reads it
     const int32_t na = live ? total : 0;
     if (tid == 0) {
         *T_out = T;

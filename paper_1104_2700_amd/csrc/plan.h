@@ -28,6 +28,16 @@ __device__ inline int upper_bound_i32(const int32_t* a, int count, int key)
     return lo;
 }
 
+__device__ inline int lower_bound_i64(const int64_t* a, int count, int64_t key)
+{
+    int lo = 0, hi = count;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 __device__ inline int lower_bound_idx(const int32_t* a, int count, int64_t key)
 {
     int lo = 0, hi = count;
@@ -134,6 +144,22 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         int32_t st, cnt;
         if (C == 1) {
             st = 0; cnt = na;
+        } else if (a.sel_clusters) {
+            // starts recorded by the selection (only when it had active
+            // particles); a cluster starting at n (empty, at the end) has
+            // its run at na
+            if (na == 0) {
+                st = 0;
+                cnt = 0;
+            } else {
+                st = o0 >= a.n ? na : a.act_start[c];
+                const int32_t nx = (c + 1 < C && o1 < a.n) ? a.act_start[c + 1] : na;
+                cnt = nx - st;
+            }
+            if (o0 >= a.n || na == 0) a.act_start[c] = st;
+            a.act_cnt[c] = cnt;
+            nact_c += cnt > 0 ? 1 : 0;
+            continue;
         } else if (a.idx == nullptr) {
             const int64_t e = o1 < na ? o1 : na;
             st = (int32_t)o0;
@@ -218,6 +244,7 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
 __device__ inline int cluster_of(const SweepArgs& a, int p)
 {
     if (a.n_clusters <= 1) return 0;
+    if (a.act_cluster) return a.act_cluster[p];
     const int i = a.idx ? a.idx[p] : p;
     return upper_bound_i64(a.offsets, a.n_clusters + 1, i) - 1;
 }

@@ -513,6 +513,15 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         SPLIT, TileS, typename std::conditional<PREC == 3, TileSP, Tile<MT>>::type>::type;
     __shared__ TT T;
     __shared__ int32_t s_item;
+    __shared__ int32_t s_ioff[kLdsClusters + 1];
+
+    // item offsets of the clusters in LDS when they fit (the item -> cluster
+    // search then costs no global round trips)
+    const bool ioff_lds = a.n_clusters > 1 && a.n_clusters <= kLdsClusters;
+    if (ioff_lds) {
+        for (int k = threadIdx.x; k <= a.n_clusters; k += kWG) s_ioff[k] = a.item_off[k];
+        __syncthreads();
+    }
 
     SweepPlan* P = a.plan;
     const int na = P->n_act;
@@ -536,8 +545,16 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         if (item >= total) break;
 
         // one system: the item layout follows from the plan alone
-        const int c = (C == 1) ? 0 : upper_bound_i32(a.item_off, C + 1, item) - 1;
-        const int local = (C == 1) ? item : item - a.item_off[c];
+        int c = 0, local = item;
+        if (C > 1) {
+            if (ioff_lds) {
+                c = upper_bound_i32(s_ioff, C + 1, item) - 1;
+                local = item - s_ioff[c];
+            } else {
+                c = upper_bound_i32(a.item_off, C + 1, item) - 1;
+                local = item - a.item_off[c];
+            }
+        }
         const int ch = (C == 1) ? P->s_max : a.chunks[c];
         const int tile_i = local / ch;
         const int k = local - tile_i * ch;
