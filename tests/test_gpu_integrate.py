@@ -314,6 +314,97 @@ def test_ensemble_force_and_lockstep(H, ctx):
             assert np.array_equal(g["t"][lo:hi], sub["t"])
 
 
+@pytest.mark.parametrize("n,prec", [(1024, 0), (6000, 1)])
+def test_run_graph_batches_match_eager(H, ctx, n, prec):
+    """hermite_run replays graphs of several steps (8 per graph, then single
+    steps for the rest of a batch): the state, the step count and the
+    counters match eager steps bit for bit, for one-block (n <= 4096) and
+    multi-block selection."""
+    x, v, m, eps2 = _c1_setup(H, n=n, seed=21)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, prec)
+    sa, sb = s0.clone(), s0.clone()
+    T_end = 1 << (TB - 3)
+    c0 = ctx.counters()
+    st_a, it_a = ctx.run(sa, eps2, params, T_end, prec, use_graph=False, sync_every=13,
+                         max_steps=45)
+    c1 = ctx.counters()
+    st_b, it_b = ctx.run(sb, eps2, params, T_end, prec, use_graph=True, sync_every=13,
+                         max_steps=45)
+    c2 = ctx.counters()
+    torch.cuda.synchronize()
+    assert st_a == st_b == 45 and it_a == it_b
+    assert c1["steps"] - c0["steps"] == c2["steps"] - c1["steps"] == 45
+    for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+        assert torch.equal(getattr(sa, key), getattr(sb, key)), key
+
+
+def test_steps_past_the_end_change_nothing(H, ctx):
+    """Once every particle is at T_end, further steps (single or in a graph
+    of several) change neither the state nor the counters."""
+    x, v, m, eps2 = _c1_setup(H, n=512, seed=23)
+    params = H.dt_params(0.04, H.DT_PAPER, 3, 20)
+    s = H.State(x, v, m, TB)
+    ctx.initialize(s, eps2, params, H.FP64)
+    T_end = 1 << (TB - 3)
+    ctx.run(s, eps2, params, T_end, H.FP64, use_graph=True, sync_every=64)
+    torch.cuda.synchronize()
+    g0 = s.to_numpy()
+    assert np.all(g0["t"] == T_end)
+    c0, h0 = ctx.counters(), ctx.block_histogram()
+    for k in range(3):
+        ctx.step(s, eps2, params, H.FP64, T_end=T_end, use_graph=(k % 2 == 0))
+    st, it = ctx.run(s, eps2, params, T_end, H.FP64, use_graph=True, sync_every=16)
+    torch.cuda.synchronize()
+    g1 = s.to_numpy()
+    assert st == 0 and it == 0
+    assert ctx.counters() == c0 and ctx.block_histogram() == h0
+    assert h0[0] == 0
+    for key in ("x", "v", "a", "j", "t", "dt"):
+        assert np.array_equal(g0[key], g1[key]), key
+
+
+def test_ensemble_multiblock_lockstep(H, ctx):
+    """An ensemble larger than one selection block (n = 6265, clusters of
+    3000, 1, 2500, 700 and 64): the selection's cluster bookkeeping across
+    blocks gives, per cluster, the oracle's block step."""
+    from oracle import oracle as O
+    from paper_1104_2700_amd import inputs
+    sizes = [3000, 1, 2500, 700, 64]
+    xs, vs, ms = [], [], []
+    for c, nc in enumerate(sizes):
+        x, v, m = inputs.plummer(nc, 700 + c)
+        xs.append(x); vs.append(v); ms.append(m)
+    x = np.concatenate(xs, 1); v = np.concatenate(vs, 1); m = np.concatenate(ms)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps2 = (4.0 / np.maximum(np.array(sizes, float), 64)) ** 2
+    cl = H.Clusters(off, eps2)
+    s = H.State(x, v, m, TB)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    ctx.initialize(s, 0.0, params, H.FP64, clusters=cl)
+    torch.cuda.synchronize()
+    for step in range(8):
+        pre = s.to_numpy()
+        T, idx = O.select(pre["t"], pre["dt"])
+        ctx.step(s, 0.0, params, H.FP64, clusters=cl, use_graph=(step % 2 == 1))
+        g = s.to_numpy()
+        for c in range(len(sizes)):
+            lo, hi = off[c], off[c + 1]
+            act = idx[(idx >= lo) & (idx < hi)]
+            if act.size == 0:
+                assert np.array_equal(g["x"][:, lo:hi], pre["x"][:, lo:hi])
+                continue
+            sub = {k: (pre[k][..., lo:hi].copy() if isinstance(pre[k], np.ndarray) else pre[k])
+                   for k in pre}
+            xp, vp = O.predict(sub["x"], sub["v"], sub["a"], sub["j"], sub["t"], T, TB)
+            la = (act - lo).astype(np.int32)
+            a1, j1, p1 = O.force(xp, vp, sub["m"], la, eps2[c])
+            O.correct(sub, la, T, xp, vp, a1, j1, p1, 0.02, 0, 3, 20)
+            assert np.abs(g["x"][:, lo:hi] - sub["x"]).max() <= 1e-14 * (np.abs(sub["x"]).max() + 1)
+            assert np.array_equal(g["t"][lo:hi], sub["t"])
+
+
 def test_counters_and_clamped(H, ctx):
     """A hard binary forces steps below 2^-k_max: the clamped count rises."""
     from paper_1104_2700_amd import inputs
