@@ -214,6 +214,40 @@ def test_lockstep_block_steps(H, ctx, prec):
         assert dt_mism <= 2
 
 
+@pytest.mark.parametrize("n", [6000, 20000])
+def test_lockstep_larger_systems(H, ctx, n):
+    """Block steps of systems that need several selection blocks (n = 6000
+    and 20000): active list, block time and corrected state equal the
+    oracle's step from the same pre-step state."""
+    from oracle import oracle as O
+    x, v, m, _ = _c1_setup(H, n=n, seed=31)
+    eps2 = (4.0 / n) ** 2
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s = H.State(x, v, m, TB)
+    ctx.initialize(s, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    for k in range(4):
+        pre = s.to_numpy()
+        T, idx = O.select(pre["t"], pre["dt"])
+        ctx.step(s, eps2, params, H.FP64, use_graph=(k % 2 == 1))
+        cnt = ctx.counters()
+        g = s.to_numpy()
+        assert cnt["T"] == T and cnt["n_act"] == idx.shape[0]
+        sub = {kk: (vv.copy() if isinstance(vv, np.ndarray) else vv) for kk, vv in pre.items()}
+        xp, vp = O.predict(sub["x"], sub["v"], sub["a"], sub["j"], sub["t"], T, TB)
+        a1, j1, p1 = O.force(xp, vp, sub["m"], idx, eps2)
+        crit_ref = np.zeros(idx.shape[0])
+        O.correct(sub, idx, T, xp, vp, a1, j1, p1, 0.02, 0, 3, 20, crit_out=crit_ref)
+        assert np.abs(g["x"] - sub["x"]).max() <= 1e-14 * (np.abs(sub["x"]).max() + 1)
+        assert np.array_equal(g["t"], sub["t"])
+        mism = g["dt"] != sub["dt"]
+        if mism.any():
+            # a power-of-two decision may differ only at a boundary tie
+            pos = np.searchsorted(idx, np.nonzero(mism)[0])
+            assert np.all(_near_boundary(crit_ref[pos], 1e-6))
+            s.dt.copy_(_dev(sub["dt"]))
+
+
 def test_graph_replay_matches_eager(H, ctx):
     x, v, m, eps2 = _c1_setup(H, n=2048, seed=11)
     params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
@@ -365,13 +399,14 @@ def test_steps_past_the_end_change_nothing(H, ctx):
         assert np.array_equal(g0[key], g1[key]), key
 
 
-def test_ensemble_multiblock_lockstep(H, ctx):
-    """An ensemble larger than one selection block (n = 6265, clusters of
-    3000, 1, 2500, 700 and 64): the selection's cluster bookkeeping across
-    blocks gives, per cluster, the oracle's block step."""
+@pytest.mark.parametrize("sizes", [[3000, 1, 2500, 700, 64], [9000, 1, 8000, 2500, 700]],
+                         ids=["n6265", "n20201"])
+def test_ensemble_multiblock_lockstep(H, ctx, sizes):
+    """Ensembles larger than one selection block (n = 6265 and 20201): the
+    selection's cluster bookkeeping across blocks gives, per cluster, the
+    oracle's block step."""
     from oracle import oracle as O
     from paper_1104_2700_amd import inputs
-    sizes = [3000, 1, 2500, 700, 64]
     xs, vs, ms = [], [], []
     for c, nc in enumerate(sizes):
         x, v, m = inputs.plummer(nc, 700 + c)
