@@ -12,6 +12,18 @@ constexpr int kSelPer = 16;                // particles per thread in select
 constexpr int kSelBlock = kWG * kSelPer;   // particles per select block
 
 // ---- block selection (procedure step 1) ---------------------------------
+// t_i + dt_i of particle i, or INT64_MAX past the end (n >= 1).  The load
+// address is clamped rather than guarded, so a thread issues all of its
+// loads before it waits for any: a guarded load compiles to a branch that
+// waits for each element in turn.
+__device__ __forceinline__ int64_t next_time(const int64_t* t, const int64_t* dt, int64_t n,
+                                             int64_t i)
+{
+    const int64_t ic = i < n ? i : n - 1;
+    const int64_t e = t[ic] + dt[ic];
+    return i < n ? e : INT64_MAX;
+}
+
 // Stage 1: per-block minimum of t_i + dt_i.
 __global__ void __launch_bounds__(kWG) sel_min_kernel(int64_t n, const int64_t* t,
                                                       const int64_t* dt,
@@ -20,12 +32,10 @@ __global__ void __launch_bounds__(kWG) sel_min_kernel(int64_t n, const int64_t* 
     __shared__ int64_t sh[kWG];
     const int64_t base = (int64_t)blockIdx.x * kSelBlock;
     int64_t v = INT64_MAX;
+#pragma unroll
     for (int r = 0; r < kSelPer; ++r) {
-        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
-        if (i < n) {
-            const int64_t e = t[i] + dt[i];
-            v = e < v ? e : v;
-        }
+        const int64_t e = next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x);
+        v = e < v ? e : v;
     }
     sh[threadIdx.x] = v;
     __syncthreads();
@@ -69,10 +79,9 @@ __global__ void __launch_bounds__(kWG) sel_count_kernel(int64_t n, const int64_t
     const int64_t T = block_min_all(block_min, nb, sh);
     const int64_t base = (int64_t)blockIdx.x * kSelBlock;
     int32_t c = 0;
-    for (int r = 0; r < kSelPer; ++r) {
-        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
-        if (i < n && t[i] + dt[i] == T) ++c;
-    }
+#pragma unroll
+    for (int r = 0; r < kSelPer; ++r)
+        c += next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x) == T ? 1 : 0;
     shc[threadIdx.x] = c;
     __syncthreads();
     for (int s = kWG / 2; s > 0; s >>= 1) {
@@ -101,9 +110,9 @@ __global__ void __launch_bounds__(kWG) sel_min_count_kernel(int64_t n, const int
     const int64_t base = (int64_t)blockIdx.x * kSelBlock;
     int64_t e[kSelPer];
     int64_t v = INT64_MAX;
+#pragma unroll
     for (int r = 0; r < kSelPer; ++r) {
-        const int64_t i = base + (int64_t)r * kWG + threadIdx.x;
-        e[r] = i < n ? t[i] + dt[i] : INT64_MAX;
+        e[r] = next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x);
         v = e[r] < v ? e[r] : v;
     }
     sh[threadIdx.x] = v;
@@ -236,9 +245,9 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
     const int64_t base = (int64_t)blockIdx.x * kSelBlock + (int64_t)threadIdx.x * kSelPer;
     bool f[kSelPer];
     int32_t c = 0;
+#pragma unroll
     for (int r = 0; r < kSelPer; ++r) {
-        const int64_t i = base + r;
-        f[r] = (i < n) && (t[i] + dt[i] == T);
+        f[r] = next_time(t, dt, n, base + r) == T;
         c += f[r] ? 1 : 0;
     }
     sh[threadIdx.x] = c;
@@ -351,8 +360,7 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
     int64_t v = INT64_MAX;
 #pragma unroll
     for (int r = 0; r < kSelPer; ++r) {
-        const int64_t i = base + r;
-        e[r] = i < n ? t[i] + dt[i] : INT64_MAX;
+        e[r] = next_time(t, dt, n, base + r);
         v = e[r] < v ? e[r] : v;
     }
     // block minimum: wave butterfly, then the kWaves wave minima

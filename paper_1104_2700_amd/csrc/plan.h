@@ -251,14 +251,30 @@ __device__ inline int cluster_of(const SweepArgs& a, int p)
 
 // Sum, in chunk order, of the partial results of active position p:
 // out = acc xyz, jerk xyz, pot.  One thread per particle.
+// Chunks are read kReduceBatch at a time from clamped addresses, so their
+// loads are in flight together; the sum is still taken in chunk order (a
+// chunk past the end adds +0.0, which leaves a sum that started at +0.0
+// unchanged bit for bit).
+constexpr int kReduceBatch = 4;
+
 __device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[7])
 {
     const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
 #pragma unroll
     for (int q = 0; q < 7; ++q) out[q] = 0.0;
-    for (int k = 0; k < ch; ++k) {
+    for (int k = 0; k < ch; k += kReduceBatch) {
+        double v[kReduceBatch][7];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) out[q] += a.partial[((int64_t)k * 7 + q) * na + p];
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int kk = k + u < ch ? k + u : ch - 1;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) v[u][q] = a.partial[((int64_t)kk * 7 + q) * na + p];
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) out[q] += k + u < ch ? v[u][q] : 0.0;
+        }
     }
 }
 

@@ -512,7 +512,6 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     using TT = typename std::conditional<
         SPLIT, TileS, typename std::conditional<PREC == 3, TileSP, Tile<MT>>::type>::type;
     __shared__ TT T;
-    __shared__ int32_t s_item;
     __shared__ int32_t s_ioff[kLdsClusters + 1];
 
     // item offsets of the clusters in LDS when they fit (the item -> cluster
@@ -538,8 +537,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     const int64_t n = a.n;
     const int64_t Tpred = a.pred_x ? *a.pred_T : 0;
 
-    // Workgroup w starts with item w; only when there are more items than
-    // workgroups do the finished ones take further items from the counter.
+    // Workgroup w takes items w, w + grid, w + 2 grid, ...
     int item = blockIdx.x;
     for (;; ) {
         if (item >= total) break;
@@ -691,11 +689,10 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                 }
             }
         }
-        if (total <= (int)gridDim.x) break;
-        __syncthreads();
-        if (tid == 0) s_item = (int32_t)gridDim.x + (int32_t)atomicAdd(&P->next_item, 1u);
-        __syncthreads();
-        item = s_item;
+        // further items round-robin: a shared counter would serialise every
+        // fetch on one address (tens of ns each across the chip)
+        item += (int)gridDim.x;
+        __syncthreads();   // the next item restages the LDS tile
     }
 }
 
