@@ -44,8 +44,9 @@ extern "C" {
 #define HERMITE_ENODEV     -2  /* no such HIP device                      */
 #define HERMITE_EHIP       -3  /* a HIP runtime call failed (message set) */
 #define HERMITE_ENOMEM     -4  /* scratch allocation failed               */
-#define HERMITE_ENONFINITE -5  /* non-finite force/jerk detected          */
-#define HERMITE_ENOTSUP    -6  /* combination not supported               */
+#define HERMITE_ENONFINITE -5  /* non-finite state detected (see          */
+                               /* hermite_check_finite, hermite_run)      */
+#define HERMITE_ENOTSUP    -6  /* reserved; not returned by this version  */
 
 /* ---- precision of the force/jerk sweep -------------------------------- */
 /* FP64 everywhere.                                                        */
@@ -238,7 +239,8 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
  * a multiple of 2^(tick_bits - k_min)), or until max_steps steps have been
  * launched (max_steps <= 0: no limit; the call can then be repeated to
  * continue).  The host reads the device block time once every sync_every
- * steps.  With use_graph != 0, runs of 8 consecutive steps are captured as
+ * steps, and then also checks the state as hermite_check_finite does:
+ * a non-finite state ends the call with HERMITE_ENONFINITE.  With use_graph != 0, runs of 8 consecutive steps are captured as
  * one graph (steps past T_end are no-ops), which removes the gap between
  * graph launches that dominates small systems.  steps_out / interactions_out (host, may be NULL) receive the
  * block-step count and the number of pair interactions (sum over steps of
@@ -249,6 +251,12 @@ int hermite_run(hermite_ctx* ctx, const hermite_state* s,
                 const hermite_dt_params* p, int64_t T_end, int use_graph,
                 int32_t sync_every, int64_t max_steps, int64_t* steps_out,
                 int64_t* interactions_out, int32_t* done_out, void* stream);
+
+/* Checks that every x, v, a, j value of the state is finite (one pass
+ * over the state; synchronises `stream`).  Returns HERMITE_ENONFINITE if
+ * one is not: with zero softening two coincident particles give an
+ * infinite force (reading of the self-term rule for eps = 0). */
+int hermite_check_finite(hermite_ctx* ctx, const hermite_state* s, void* stream);
 
 /* Cumulative device counters since creation (synchronises `stream`):
  * out[0] block steps, out[1] interactions, out[2] clamped steps,

@@ -168,6 +168,11 @@ hipError_t launch_copy2(int64_t count, const double* src0, double* dst0,
 
 hipError_t launch_iota(int32_t count, int32_t* out, hipStream_t st);
 
+// Clears *flag, then sets it when any x, v, a, j value of the state is not
+// finite (not graph-safe: clears with hipMemsetAsync).
+hipError_t launch_check_finite(int64_t n, const double* x, const double* v, const double* a,
+                               const double* j, int32_t* flag, hipStream_t st);
+
 int sweep_occupancy(int precision, int variant, bool pot_only);
 
 hipError_t launch_energy_reduce(int64_t n, int n_clusters,

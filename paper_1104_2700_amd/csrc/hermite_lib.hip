@@ -73,7 +73,7 @@ struct hermite_ctx {
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     Buf sel_min, sel_cnt;
-    Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket;
+    Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     std::vector<GraphEntry> graphs;
 };
 
@@ -390,7 +390,7 @@ int hermite_destroy(hermite_ctx* c)
     Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
                    &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
-                   &c->ticket};
+                   &c->ticket, &c->flag};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -631,6 +631,28 @@ static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_cl
     return HERMITE_OK;
 }
 
+// Enqueues the finiteness check of s and reads the flag (synchronises).
+static int check_finite(hermite_ctx* c, const hermite_state* s, hipStream_t st, int* bad)
+{
+    CHECK(ensure(c, c->flag, sizeof(int32_t)));
+    HIP_OK(launch_check_finite(s->n, s->x, s->v, s->a, s->j, (int32_t*)c->flag.p, st));
+    int32_t h = 0;
+    HIP_OK(hipMemcpyAsync(&h, c->flag.p, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *bad = h != 0;
+    return HERMITE_OK;
+}
+
+int hermite_check_finite(hermite_ctx* c, const hermite_state* s, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    int bad = 0;
+    CHECK(check_finite(c, s, (hipStream_t)stream, &bad));
+    if (bad) return fail(HERMITE_ENONFINITE, "non-finite position, velocity, acceleration or jerk");
+    return HERMITE_OK;
+}
+
 int hermite_counters(hermite_ctx* c, int64_t out[5], void* stream)
 {
     CHECK(check_ctx(c));
@@ -686,7 +708,12 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
         int32_t na = 0;
         HIP_OK(hipMemcpyAsync(&T, c->step_T.p, sizeof T, hipMemcpyDeviceToHost, st));
         HIP_OK(hipMemcpyAsync(&na, c->step_na.p, sizeof na, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        int bad = 0;
+        CHECK(check_finite(c, s, st, &bad));   // synchronises st
+        if (bad)
+            return fail(HERMITE_ENONFINITE,
+                        "non-finite state after block time %lld ticks (e.g. coincident "
+                        "particles with zero softening)", (long long)T);
         if (na == 0 || T >= T_end) {
             done = 1;
             break;

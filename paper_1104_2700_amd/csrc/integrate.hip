@@ -722,6 +722,33 @@ hipError_t launch_iota(int32_t count, int32_t* out, hipStream_t st)
     return hipGetLastError();
 }
 
+// Sets *flag when any of the 12 n values of x, v, a, j is not finite
+// (grid-stride; one non-returning atomic per wave that saw one).
+__global__ void __launch_bounds__(kWG) nonfinite_kernel(int64_t count, const double* x,
+                                                        const double* v, const double* a,
+                                                        const double* j, int32_t* flag)
+{
+    bool bad = false;
+    for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * kWG) {
+        bad |= !__builtin_isfinite(x[k]) || !__builtin_isfinite(v[k]) ||
+               !__builtin_isfinite(a[k]) || !__builtin_isfinite(j[k]);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(int64_t n, const double* x, const double* v, const double* a,
+                               const double* j, int32_t* flag, hipStream_t st)
+{
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
+    const int64_t count = 3 * n;
+    const int64_t nb = nblocks(count, kWG);
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(kWG), 0,
+                       st, count, x, v, a, j, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy_reduce(int64_t n, int n_clusters,
                                 const int64_t* offsets, const double* m,
                                 const double* v, const double* phi,

@@ -75,6 +75,7 @@ _SIGS = {
     "hermite_force_jerk": ([_P, _PS, _PC, _P, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _P]),
     "hermite_correct": ([_P, _PS, _P, _P, _i32, _P, _i64, _P, _P, _P, _PD, _P, _P]),
     "hermite_init_dt": ([_P, _PS, _PD, _P]),
+    "hermite_check_finite": ([_P, _PS, _P]),
     "hermite_initialize": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _P]),
     "hermite_energy": ([_P, _PS, _PC, _d, _P, _P]),
     "hermite_step": ([_P, _PS, _PC, _d, ctypes.c_int, _PD, _i64, ctypes.c_int, _P]),
@@ -300,6 +301,14 @@ class Context:
         _check(lib.hermite_block_histogram(self.h, out, _stream(stream)),
                "hermite_block_histogram")
         return list(out)
+
+    def check_finite(self, s: State, stream=None):
+        """True when every x, v, a, j value is finite (synchronises)."""
+        rc = lib.hermite_check_finite(self.h, ctypes.byref(s.c()), _stream(stream))
+        if rc == ENONFINITE:
+            return False
+        _check(rc, "hermite_check_finite")
+        return True
 
     def counters(self, stream=None):
         out = (_i64 * 5)()

@@ -50,6 +50,8 @@ def test_errors_without_touching_a_device(lib):
     assert rc == -1
     lib.hermite_destroy.argtypes = [ctypes.c_void_p]
     assert lib.hermite_destroy(None) == 0
+    lib.hermite_check_finite.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.hermite_check_finite(None, None, None) == -1
 
 
 def test_binding_names_match_header():

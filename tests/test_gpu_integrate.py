@@ -440,6 +440,28 @@ def test_ensemble_multiblock_lockstep(H, ctx, sizes):
             assert np.array_equal(g["t"][lo:hi], sub["t"])
 
 
+def test_check_finite_and_run_stops_on_nonfinite(H, ctx):
+    """hermite_check_finite flags a NaN anywhere in x, v, a, j; a run of a
+    system with two coincident particles and zero softening (infinite
+    force) stops with HERMITE_ENONFINITE instead of integrating on."""
+    x, v, m, eps2 = _c1_setup(H, n=256, seed=41)
+    s = H.State(x, v, m, TB)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    ctx.initialize(s, eps2, params, H.FP64)
+    assert ctx.check_finite(s)
+    for key, d, i in (("x", 1, 7), ("v", 2, 200), ("a", 0, 255), ("j", 2, 0)):
+        bad = s.clone()
+        getattr(bad, key)[d, i] = float("nan")
+        assert not ctx.check_finite(bad), key
+    x2 = x.copy()
+    x2[:, 5] = x2[:, 9]                     # particles 5 and 9 coincide
+    s2 = H.State(x2, v, m, TB)
+    ctx.initialize(s2, 0.0, params, H.FP64)
+    with pytest.raises(H.HermiteError) as err:
+        ctx.run(s2, 0.0, params, 1 << (TB - 3), H.FP64, use_graph=True, sync_every=16)
+    assert err.value.code == H.ENONFINITE
+
+
 def test_counters_and_clamped(H, ctx):
     """A hard binary forces steps below 2^-k_max: the clamped count rises."""
     from paper_1104_2700_amd import inputs
