@@ -271,6 +271,26 @@ def cpu_leg(x, v, m, eps2, results, target_s):
            "kind": "oracle",
            "sample": "%d active particles x %d j of the N=65536 Plummer state "
                      "(FP64, Neumaier sums), %.1f s" % (n_i, N, secs)}
+    # the same sweep on one host thread, on a smaller sample
+    prev = O.threads()
+    O.threads(1)
+    one_idx = eval_idx[:256]
+    t4 = time.perf_counter()
+    O.force(x, v, m, one_idx, eps2)
+    t5 = time.perf_counter()
+    O.threads(prev)
+    cpu["single_thread"] = {"value": one_idx.shape[0] * N / (t5 - t4), "unit": "interactions/s",
+                            "cores": 1, "sample": "256 active particles x %d j" % N}
+    # the whole N = 1024 run (Plummer seed 1, eps = 1/64, eta = 0.02, t = 0 -> 0.125)
+    from paper_1104_2700_amd import inputs
+    x1, v1, m1 = inputs.plummer(1024, 1)
+    st = O.new_state(x1, v1, m1, TB)
+    t6 = time.perf_counter()
+    stats = O.run(st, 1 << (TB - 3), (1.0 / 64) ** 2, ETA, O.FORM_PAPER, 3, 20)
+    t7 = time.perf_counter()
+    cpu["n1024_run"] = {"value": stats["interactions"] / (t7 - t6), "unit": "interactions/s",
+                        "cores": cores, "wall_s": t7 - t6, "block_steps": stats["steps"],
+                        "gflops_60": FLOPS_PAPER * stats["interactions"] / (t7 - t6) / 1e9}
     acc = {}
     for p, r in results.items():
         A, J, P = r["out"]

@@ -27,6 +27,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Neumaier compensated sum (Neumaier 1974).                            */
@@ -327,4 +330,20 @@ void oracle_energy(int64_t n, const double* pos, const double* vel,
     }
     *K = nsum_get(&k);
     *W = nsum_get(&w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Thread count of the parallel loops (timing only; results do not     */
+/* depend on it).  n < 1 leaves it unchanged.  Returns the count now   */
+/* in effect.                                                          */
+/* ------------------------------------------------------------------ */
+int oracle_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

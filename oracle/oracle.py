@@ -63,7 +63,15 @@ def configure(lib):
     lib.oracle_init_dt.restype = i64
     lib.oracle_energy.argtypes = [i64, P, P, P, d, P, P, P, P, P, P]
     lib.oracle_energy.restype = None
+    lib.oracle_threads.argtypes = [i32]
+    lib.oracle_threads.restype = i32
     return lib
+
+
+def threads(n=0):
+    """Sets the oracle's thread count (n >= 1) and returns the count in
+    effect; the results do not depend on it (the j order is fixed)."""
+    return int(_L().oracle_threads(int(n)))
 
 
 def compile_source(src_path, out_path):
