@@ -26,7 +26,6 @@ struct SweepPlan {
     int32_t s_max;        // largest number of j-chunks of any cluster
     int64_t jc;           // j-chunk length (multiple of kTJ)
     int32_t total_items;  // work items (cluster, i-tile, j-chunk)
-    uint32_t next_item;   // dynamic work counter of the persistent grid
 };
 
 // Everything the plan, sweep and reduce kernels read.  Passed by value.

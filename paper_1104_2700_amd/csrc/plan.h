@@ -125,7 +125,6 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
             P->s_max = ch;
             P->jc = jc;
             P->total_items = tiles * ch;
-            P->next_item = 0u;
             if (a.counters && na > 0)
                 atomicAdd((unsigned long long*)&a.counters[1],
                           (unsigned long long)((int64_t)na * a.n));
@@ -234,7 +233,6 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         P->s_max = s_cmax[kWG - 1];
         P->jc = jc;
         P->total_items = s_items[kWG - 1];
-        P->next_item = 0u;
         if (a.counters && s_inter[kWG - 1] > 0)
             atomicAdd((unsigned long long*)&a.counters[1],
                       (unsigned long long)s_inter[kWG - 1]);

@@ -8,10 +8,11 @@
 //
 // Design (GPU analogue of the paper's i-in-registers, j-streamed loop of
 // Section 3.3):
-//  * Work is a list of items (cluster, i-tile, j-chunk).  A persistent grid
-//    of workgroups pulls items from a device counter, so one launch serves
-//    any active count, ragged clusters and graph replays.
-//  * Each lane holds one active particle in registers.  When the active
+//  * Work is a list of items (cluster, i-tile, j-chunk) that the plan builds
+//    on the device.  A persistent grid takes them round-robin (workgroup w
+//    takes w, w + grid, ...), so one launch serves any active count, ragged
+//    clusters and graph replays.
+//  * Each lane holds one or two active particles in registers.  When the active
 //    block is small, L lanes of a wave share one particle and take every
 //    L-th j; their sums are combined by a wave-shuffle butterfly.  Larger
 //    splits go across workgroups (j-chunks) and are added in a fixed order
