@@ -1,6 +1,10 @@
 """Whole-run workloads on one GPU (block-timestep integrations).
 
-    python -m paper_1104_2700_amd.workloads <name> [--t-end T] [--out file.json]
+    python -m paper_1104_2700_amd.workloads <name> [--t-end T] [--start-div D] [--out file.json]
+
+(--start-div D: first steps eta_f/D |a|/|j| instead of eta_f |a|/|j|; the
+start-up rule is a reading, and the default factor lets the first step
+dominate a short run's energy error.)
 
 Names:
   c1  Plummer N = 1024, eps = 1/64, eta = 0.02, FP64, t = 0 -> 0.125
@@ -45,8 +49,17 @@ from . import hermite as H
 from . import inputs
 
 TB = 20          # time tick 2^-20
+START_DIV = 0    # start-up factor = steady factor / START_DIV (0: the steady factor)
 FORMS = {"paper": H.DT_PAPER, "aarseth": H.DT_AARSETH}
 K_MIN, K_MAX = 3, 20
+
+
+def _params(eta, form=H.DT_PAPER):
+    """Timestep parameters of the whole-run workloads (k in [3, 20]); the
+    start-up factor follows START_DIV (the --start-div option)."""
+    eta_f = eta if form == H.DT_PAPER else math.sqrt(eta)
+    return H.dt_params(eta, form, K_MIN, K_MAX,
+                       eta_init=(eta_f / START_DIV) if START_DIV else 0.0)
 
 
 def _log(msg):
@@ -120,7 +133,7 @@ def _plummer_state(n, seed):
 def c1(ctx, t_end=0.125):
     s = _plummer_state(1024, 1)
     eps2 = (1.0 / 64) ** 2
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     ctx.initialize(s, eps2, p, H.FP64)
     return {"config": "plummer_n1024_fp64", "run": block_run(ctx, s, eps2, p, t_end, H.FP64,
                                                              label="c1")}
@@ -130,7 +143,7 @@ def c2(ctx, t_end=1.0):
     n = 16384
     s = _plummer_state(n, 2)
     eps2 = (4.0 / n) ** 2
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     s.xp.copy_(s.x)
     s.vp.copy_(s.v)
     ms = sweep_time(ctx, s, eps2, H.FP64)
@@ -160,7 +173,7 @@ def c3(ctx, t_end=1.0):
         curve.append(row)
         _log("  c3 n_act %6d  fp64 %.1f us  mixed %.1f us" % (na, row["fp64_us"], row["mixed_us"]))
         na *= 2
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     ctx.initialize(s, eps2, p, H.MIXED)
     run = block_run(ctx, s, eps2, p, t_end, H.MIXED, label="c3")
     return {"config": "plummer_n65536_mixed", "latency_curve": curve, "run": run}
@@ -171,7 +184,7 @@ def c4(ctx, t_end=0.5, serial_t_end=0.125, n_clusters=256, serial_clusters=16):
     x, v, m, off, eps = inputs.ensemble(n_clusters, 4)
     eps2 = eps ** 2
     sizes = np.diff(off)
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     out = {"config": "ensemble_%d_clusters_mixed" % n_clusters,
            "n_total": int(off[-1]), "sum_Nc2": float(np.sum(sizes.astype(float) ** 2)),
            "sizes_min_max": [int(sizes.min()), int(sizes.max())]}
@@ -221,7 +234,7 @@ def c5(ctx, t_end=0.25):
     x, v, m = inputs.plummer_imf_binaries(n, 5)
     s = H.State(x, v, m, TB)
     eps2 = 1e-5 ** 2
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     ctx.initialize(s, eps2, p, H.MIXED_2F)
     return {"config": "plummer_imf_binaries_n131072_mixed2f",
             "run": block_run(ctx, s, eps2, p, t_end, H.MIXED_2F, label="c5")}
@@ -323,7 +336,7 @@ def e2(ctx, t_end=0.125, n=262144, seed=6):
     side: the paper finds no difference in energy conservation (Section 4)."""
     x, v, m = inputs.plummer(n, seed)
     eps2 = (4.0 / n) ** 2
-    p = H.dt_params(0.02, H.DT_PAPER, K_MIN, K_MAX)
+    p = _params(0.02)
     out = {"config": "plummer_n%d_jerk_sum_precision" % n, "t_end": t_end, "runs": {}}
     for pname in ("mixed", "mixed_sp"):
         s = H.State(x, v, m, TB)
@@ -338,7 +351,7 @@ def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7, form="paper")
     against N, from t = 0 to t_end (Section 5, Fig. of GFLOPS vs N); eta =
     0.02 in the printed form eta sqrt(R) or the classic sqrt(eta R)."""
     rows = []
-    p = H.dt_params(0.02, FORMS[form], K_MIN, K_MAX)
+    p = _params(0.02, FORMS[form])
     for n in ns:
         x, v, m = inputs.plummer(n, seed)
         eps2 = (4.0 / n) ** 2
@@ -364,8 +377,12 @@ def main(argv=None):
     ap.add_argument("--serial-clusters", type=int, default=None)
     ap.add_argument("--form", choices=sorted(FORMS), default=None,
                     help="timestep criterion form (e4 only)")
+    ap.add_argument("--start-div", type=float, default=0.0,
+                    help="start-up factor = steady factor / this (0: the steady factor)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    global START_DIV
+    START_DIV = a.start_div
     ctx = H.Context(0)
     kw = {}
     if a.t_end is not None:
@@ -379,6 +396,7 @@ def main(argv=None):
     _log("workload %s %s" % (a.name, kw))
     res = RUNNERS[a.name](ctx, **kw)
     res["device"] = torch.cuda.get_device_name(0)
+    res["start_div"] = START_DIV
     txt = json.dumps(res)
     if a.out:
         with open(a.out, "w") as f:
