@@ -72,6 +72,15 @@ struct SweepArgs {
     const int64_t* pred_t;
     const int64_t* pred_T;
     double tick;               // 2^-tick_bits
+    // Selection fused into the sweep (one system of n <= kSelBlock, block
+    // step path): every workgroup takes the block time and the active list
+    // from t (pred_t) and sel_dt itself; workgroup 0 publishes the list,
+    // n_act, T, the plan and the counters for the corrector.
+    const int64_t* sel_dt;
+    int64_t sel_T_end;
+    int32_t* sel_idx_out;      // [n]
+    int32_t* sel_na_out;
+    int64_t* sel_T_out;
     // outputs of the reduce stage
     double* acc;               // [3][n_act_max]
     double* jerk;              // [3][n_act_max] or null
@@ -153,6 +162,20 @@ hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, in
                               int32_t* idx, int32_t* n_act, int64_t* T, int64_t* block_min,
                               int32_t* block_cnt, int64_t* counters, uint32_t* ticket,
                               const SweepArgs& sa, hipStream_t st);
+// Largest system whose sweep workgroups select the block themselves: every
+// workgroup reads all t, dt, so the fusion pays only while that read is
+// small (measured: faster at 1024 and 2048, slower at 4096).
+constexpr int kFusedSelMax = 2048;
+
+// Largest number of work items the plan gives for any active count of a
+// single system (host; sizes the grid of the fused select + sweep launch).
+int max_plan_items(const SweepArgs& a);
+
+// Selection fused into the sweep (sel_* fields of a set, n <= kFusedSelMax,
+// one system).
+hipError_t launch_select_sweep(const SweepArgs& a, int precision, int variant, int grid,
+                               hipStream_t st);
+
 hipError_t launch_sweep_only(const SweepArgs& a, int precision, int variant, int grid,
                              hipStream_t st);
 hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);

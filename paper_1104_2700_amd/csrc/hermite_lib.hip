@@ -75,6 +75,11 @@ struct hermite_ctx {
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     std::vector<GraphEntry> graphs;
+    // grid of the fused select + sweep for the last shape it was sized for
+    struct {
+        int64_t n = -1, cap = 0;
+        int32_t lanes = 0, min_j = 0, ipl = 0, grid = 0;
+    } fused;
 };
 
 namespace {
@@ -284,11 +289,33 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     a.pred_t = s->t;
     a.pred_T = T;
     a.tick = std::ldexp(1.0, -s->tick_bits);
-    HIP_OK(launch_step_select(n, s->t, s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
-                              (int32_t*)c->sel_cnt.p, counters, (uint32_t*)c->ticket.p, a,
-                              st));
-    HIP_OK(launch_sweep_only(a, precision, tu.variant, std::max(1, c->n_cu * tu.wg_per_cu),
-                             st));
+    const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
+    if (!cl && n <= kFusedSelMax) {
+        // one small system: every sweep workgroup selects the block itself
+        // (no selection kernel); the grid is capped at the most items any
+        // active count can give, so idle workgroups do no selection
+        a.sel_dt = s->dt;
+        a.sel_T_end = T_end;
+        a.sel_idx_out = idx;
+        a.sel_na_out = na;
+        a.sel_T_out = T;
+        auto& f = c->fused;
+        if (f.n != n || f.cap != a.partial_cap || f.lanes != a.target_lanes ||
+            f.min_j != a.min_j_per_lane || f.ipl != a.ipl) {
+            f.n = n;
+            f.cap = a.partial_cap;
+            f.lanes = a.target_lanes;
+            f.min_j = a.min_j_per_lane;
+            f.ipl = a.ipl;
+            f.grid = max_plan_items(a);
+        }
+        HIP_OK(launch_select_sweep(a, precision, tu.variant, std::min(grid, f.grid), st));
+    } else {
+        HIP_OK(launch_step_select(n, s->t, s->dt, T_end, idx, na, T, (int64_t*)c->sel_min.p,
+                                  (int32_t*)c->sel_cnt.p, counters, (uint32_t*)c->ticket.p, a,
+                                  st));
+        HIP_OK(launch_sweep_only(a, precision, tu.variant, grid, st));
+    }
     CorrectArgs ca;
     std::memset(&ca, 0, sizeof ca);
     ca.n = n;

@@ -265,21 +265,6 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
     return off + block_total;
 }
 
-// Counts a block step.  A step with no active particle is one past T_end
-// (every live step has at least one): it leaves the counters untouched, so
-// replaying extra steps after the end changes nothing.
-__device__ void count_step(int64_t* counters, int64_t T, int32_t na)
-{
-    if (counters && na > 0) {
-        // non-returning atomics: the caller does not wait for the update
-        atomicAdd((unsigned long long*)&counters[0], 1ull);
-        counters[3] = T;
-        counters[4] = na;
-        const int bin = 32 - __clz(na);                 // block-size histogram
-        atomicAdd((unsigned long long*)&counters[kHistBase + bin], 1ull);
-    }
-}
-
 __global__ void __launch_bounds__(kWG) sel_write_kernel(int64_t n, const int64_t* t,
                                                         const int64_t* dt,
                                                         const int32_t* block_cnt,

@@ -48,6 +48,79 @@ __device__ inline int lower_bound_idx(const int32_t* a, int count, int64_t key)
     return lo;
 }
 
+// Counts a block step.  A step with no active particle is one past T_end
+// (every live step has at least one): it leaves the counters untouched, so
+// replaying extra steps after the end changes nothing.
+__device__ inline void count_step(int64_t* counters, int64_t T, int32_t na)
+{
+    if (counters && na > 0) {
+        // non-returning atomics: the caller does not wait for the update
+        atomicAdd((unsigned long long*)&counters[0], 1ull);
+        counters[3] = T;
+        counters[4] = na;
+        const int bin = 32 - __clz(na);                 // block-size histogram
+        atomicAdd((unsigned long long*)&counters[kHistBase + bin], 1ull);
+    }
+}
+
+// One workgroup selects the block of a system of n <= kFusedSelMax
+// particles (procedure step 1): T = min_i (t_i + dt_i) into *T_out and the
+// active indices, ascending, into s_idx (LDS).  Returns n_act, or 0 when
+// T > T_end.  Each thread owns kFusedSelMax / kWG consecutive particles;
+// their loads use clamped addresses so that all are in flight together.
+// All threads call it.
+__device__ inline int32_t select_in_lds(const int64_t* t, const int64_t* dt, int64_t n,
+                                        int64_t T_end, int32_t* s_idx, int64_t* T_out)
+{
+    constexpr int kPer = kFusedSelMax / kWG;
+    constexpr int kWaves = kWG / 64;
+    __shared__ int64_t s_min[kWaves];
+    __shared__ int32_t s_cnt[kWaves];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t base = (int64_t)tid * kPer;
+    int64_t e[kPer];
+    int64_t v = INT64_MAX;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int64_t i = base + r;
+        const int64_t ic = i < n ? i : n - 1;
+        const int64_t x = t[ic] + dt[ic];
+        e[r] = i < n ? x : INT64_MAX;
+        v = e[r] < v ? e[r] : v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    if (lane == 0) s_min[wave] = v;
+    __syncthreads();
+    int64_t T = s_min[0];
+    for (int w = 1; w < kWaves; ++w) T = s_min[w] < T ? s_min[w] : T;
+    int32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) c += e[r] == T ? 1 : 0;
+    int32_t x = c;                      // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    if (lane == 63) s_cnt[wave] = x;
+    __syncthreads();
+    int32_t pos = x - c, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        pos += w < wave ? s_cnt[w] : 0;
+        total += s_cnt[w];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+        if (e[r] == T) s_idx[pos++] = (int32_t)(base + r);
+    __syncthreads();
+    *T_out = T;
+    return T <= T_end ? total : 0;
+}
+
 // ------------------------------------------------------------------------
 // Plan: one workgroup (all kWG threads must call this) turns the active
 // count into a split (lanes per particle L, chunk length jc) and a work
@@ -55,9 +128,10 @@ __device__ inline int lower_bound_idx(const int32_t* a, int count, int64_t key)
 // interaction count to the counters.
 // ------------------------------------------------------------------------
 // The split for na active particles of (at most) c_act active clusters:
-// lanes per particle L, particles per item ti, chunk length jc.
-__device__ inline void plan_split(const SweepArgs& a, int32_t na, int64_t c_act, int32_t* L_out,
-                                  int32_t* ti_out, int64_t* jc_out)
+// lanes per particle L, particles per item ti, chunk length jc.  (Also
+// evaluated on the host, to size the grid of the fused select + sweep.)
+__host__ __device__ inline void plan_split(const SweepArgs& a, int32_t na, int64_t c_act,
+                                           int32_t* L_out, int32_t* ti_out, int64_t* jc_out)
 {
     const int C = a.n_clusters;
     // Work items wanted (about one per resident workgroup slot, times the

@@ -504,9 +504,13 @@ __device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int6
 //   IPL: active particles per lane (1 or 2).  Lane `slot` of an item holds
 //   the item's particles slot, slot + kWG/L, ...
 // ------------------------------------------------------------------------
-template <int PREC, bool POT_ONLY, int IPL, bool SPLIT>
+// SEL: the workgroup first selects the block itself (one system of
+// n <= kFusedSelMax; the active list stays in LDS) and computes the plan;
+// workgroup 0 publishes list, n_act, T, plan and counters for the corrector.
+template <int PREC, bool POT_ONLY, int IPL, bool SPLIT, bool SEL = false>
 __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
 {
+    static_assert(!SEL || !POT_ONLY, "the fused selection is for block steps");
     static_assert(!SPLIT || (PREC == 1 || PREC == 2), "split form is for the mixed modes");
     using MT = typename std::conditional<PREC == 0, double, float>::type;
     using RUN = typename std::conditional<PREC == 2, Sum2F, SumD>::type;
@@ -524,19 +528,52 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     }
 
     SweepPlan* P = a.plan;
-    const int na = P->n_act;
-    if (na == 0) return;
-    const int L = P->L;
-    const int ti = P->ti;
-    const int rows = kWG / L;          // lanes' slots per particle row
-    const int64_t jc = P->jc;
-    const int total = P->total_items;
     const int tid = threadIdx.x;
+    int na, L, ti, s_max, total;
+    int64_t jc, Tpred;
+    const int32_t* idx_lds = nullptr;
+    if constexpr (SEL) {
+        __shared__ int32_t s_idx[kFusedSelMax];
+        na = select_in_lds(a.pred_t, a.sel_dt, a.n, a.sel_T_end, s_idx, &Tpred);
+        int32_t L_, ti_;
+        plan_split(a, na, 1, &L_, &ti_, &jc);
+        L = L_;
+        ti = ti_;
+        s_max = na > 0 ? (int)((a.n + jc - 1) / jc) : 0;
+        total = ((na + ti - 1) / ti) * s_max;
+        idx_lds = s_idx;
+        if (blockIdx.x == 0) {
+            for (int p = tid; p < na; p += kWG) a.sel_idx_out[p] = s_idx[p];
+            if (tid == 0) {
+                *a.sel_na_out = na;
+                *a.sel_T_out = Tpred;
+                P->n_act = na;
+                P->L = L;
+                P->ti = ti;
+                P->s_max = s_max;
+                P->jc = jc;
+                P->total_items = total;
+                count_step(a.counters, Tpred, na);
+                if (a.counters && na > 0)
+                    atomicAdd((unsigned long long*)&a.counters[1],
+                              (unsigned long long)((int64_t)na * a.n));
+            }
+        }
+    } else {
+        na = P->n_act;
+        L = P->L;
+        ti = P->ti;
+        jc = P->jc;
+        s_max = P->s_max;
+        total = P->total_items;
+        Tpred = a.pred_x ? *a.pred_T : 0;
+    }
+    if (na == 0) return;
+    const int rows = kWG / L;          // lanes' slots per particle row
     const int slot = tid / L;
     const int sub = tid & (L - 1);
     const int C = a.n_clusters;
     const int64_t n = a.n;
-    const int64_t Tpred = a.pred_x ? *a.pred_T : 0;
 
     // Workgroup w takes items w, w + grid, w + 2 grid, ...
     int item = blockIdx.x;
@@ -554,7 +591,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                 local = item - a.item_off[c];
             }
         }
-        const int ch = (C == 1) ? P->s_max : a.chunks[c];
+        const int ch = (C == 1) ? s_max : a.chunks[c];
         const int tile_i = local / ch;
         const int k = local - tile_i * ch;
         const int p0 = ((C == 1) ? 0 : a.act_start[c]) + tile_i * ti;
@@ -579,7 +616,8 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             const int pos = slot + q * rows;
             valid[q] = pos < pcnt;
             pp[q] = p0 + (valid[q] ? pos : 0);
-            ii[q] = a.idx ? a.idx[pp[q]] : pp[q];
+            if constexpr (SEL) ii[q] = idx_lds[pp[q]];
+            else ii[q] = a.idx ? a.idx[pp[q]] : pp[q];
             double r[3], w[3];
             fetch_particle(a, ii[q], Tpred, r, w);
             I[q].x = r[0]; I[q].y = r[1]; I[q].z = r[2];
@@ -742,6 +780,23 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
 
 typedef void (*SweepFn)(SweepArgs);
 
+// The fused select + sweep instantiations (block steps of one small system).
+SweepFn sweep_sel_fn(int precision, int variant)
+{
+    const bool two = (variant & 1) != 0;
+    const bool spl = (variant & 2) != 0;
+    if (precision == 0)
+        return two ? sweep_kernel<0, false, 2, false, true> : sweep_kernel<0, false, 1, false, true>;
+    if (precision == 3)
+        return two ? sweep_kernel<3, false, 2, false, true> : sweep_kernel<3, false, 1, false, true>;
+    if (precision == 1) {
+        if (spl) return two ? sweep_kernel<1, false, 2, true, true> : sweep_kernel<1, false, 1, true, true>;
+        return two ? sweep_kernel<1, false, 2, false, true> : sweep_kernel<1, false, 1, false, true>;
+    }
+    if (spl) return two ? sweep_kernel<2, false, 2, true, true> : sweep_kernel<2, false, 1, true, true>;
+    return two ? sweep_kernel<2, false, 2, false, true> : sweep_kernel<2, false, 1, false, true>;
+}
+
 // variant: bit 0 -> two active particles per lane; bit 1 -> split
 // differences (MIXED and MIXED_2F only; FP64 and MIXED_SP ignore it).
 SweepFn sweep_fn(int precision, int variant, bool pot_only)
@@ -762,6 +817,29 @@ SweepFn sweep_fn(int precision, int variant, bool pot_only)
 }
 
 }  // namespace
+
+int max_plan_items(const SweepArgs& a)
+{
+    int best = 0;
+    const int32_t top = a.n_act_max < (int32_t)a.n ? a.n_act_max : (int32_t)a.n;
+    for (int32_t na = 1; na <= top; ++na) {
+        int32_t L, ti;
+        int64_t jc;
+        plan_split(a, na, 1, &L, &ti, &jc);
+        const int64_t items = (int64_t)((na + ti - 1) / ti) * ((a.n + jc - 1) / jc);
+        if (items > best) best = (int)items;
+    }
+    return best > 0 ? best : 1;
+}
+
+hipError_t launch_select_sweep(const SweepArgs& a_in, int precision, int variant, int grid,
+                               hipStream_t st)
+{
+    SweepArgs a = a_in;
+    a.ipl = (variant & 1) ? 2 : 1;
+    hipLaunchKernelGGL(sweep_sel_fn(precision, variant), dim3(grid), dim3(kWG), 0, st, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep_only(const SweepArgs& a_in, int precision, int variant, int grid,
                              hipStream_t st)

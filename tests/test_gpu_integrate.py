@@ -214,11 +214,12 @@ def test_lockstep_block_steps(H, ctx, prec):
         assert dt_mism <= 2
 
 
-@pytest.mark.parametrize("n", [6000, 20000])
+@pytest.mark.parametrize("n", [3, 3000, 6000, 20000])
 def test_lockstep_larger_systems(H, ctx, n):
-    """Block steps of systems that need several selection blocks (n = 6000
-    and 20000): active list, block time and corrected state equal the
-    oracle's step from the same pre-step state."""
+    """Block steps of systems on each selection path: selection fused into
+    the sweep (n = 3), one selection workgroup (n = 3000), several selection
+    blocks (n = 6000, 20000): active list, block time and corrected state
+    equal the oracle's step from the same pre-step state."""
     from oracle import oracle as O
     x, v, m, _ = _c1_setup(H, n=n, seed=31)
     eps2 = (4.0 / n) ** 2
