@@ -282,7 +282,10 @@ int hermite_set_tuning(hermite_ctx* ctx, int precision,
  * events at the predicted positions s->xp, s->vp, and keep the fastest
  * whose results stay as close to an FP64 sweep as the precision allows
  * (FP64: 1e-13 relative; mixed: 1e-6 or 1.5 times the default shape's
- * deviation, whichever is larger).  Installs it in the context and, if
+ * deviation, whichever is larger).  Every candidate is screened with a few
+ * launches; the six fastest and the default are then timed again in three
+ * interleaved rounds, and the lowest median wins.  Installs it in the
+ * context and, if
  * cache_path is non-NULL, merges it into that JSON file keyed by device
  * architecture, HIP version, precision and power-of-two size buckets of
  * n and n_act.  Synchronises. */

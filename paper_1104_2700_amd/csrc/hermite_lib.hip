@@ -925,6 +925,7 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
     int rc = HERMITE_OK;
     double best_us = 0.0;
     hermite_tuning best = base;
+    std::vector<std::pair<double, hermite_tuning>> passed;   // screened candidates
     const double tol = precision == HERMITE_FP64 ? 1e-13 : 1e-6;
     double limit[3] = {tol, tol, tol};
     std::vector<double> ref64(7 * (size_t)n_act);
@@ -956,13 +957,37 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
                         errs(got, ref64, ge);
                         const bool ok = ge[0] <= limit[0] && ge[1] <= limit[1] &&
                                         ge[2] <= limit[2];
-                        if (ok && us < best_us) {
-                            best_us = us;
-                            best = tu;
-                        }
+                        if (ok) passed.emplace_back(us, tu);
                     }
                     if (rc != HERMITE_OK) break;
                 }
+            }
+        }
+        if (rc != HERMITE_OK) break;
+        // A 3-launch screen is noisy, and the minimum over ~100 candidates
+        // picks lucky timings: the fastest kFinalists (and the default) are
+        // timed again in kRounds interleaved rounds of kFinalReps launches,
+        // and the lowest median wins.
+        constexpr size_t kFinalists = 6;
+        constexpr int kRounds = 3, kFinalReps = 10;
+        std::sort(passed.begin(), passed.end(),
+                  [](const std::pair<double, hermite_tuning>& x,
+                     const std::pair<double, hermite_tuning>& y) { return x.first < y.first; });
+        if (passed.size() > kFinalists) passed.resize(kFinalists);
+        passed.emplace_back(best_us, base);
+        std::vector<std::vector<double>> t(passed.size());
+        for (int r = 0; r < kRounds && rc == HERMITE_OK; ++r)
+            for (size_t k = 0; k < passed.size() && rc == HERMITE_OK; ++k) {
+                rc = run(passed[k].second, kFinalReps, &us, nullptr);
+                t[k].push_back(us);
+            }
+        if (rc != HERMITE_OK) break;
+        for (size_t k = 0; k < passed.size(); ++k) {
+            std::sort(t[k].begin(), t[k].end());
+            const double med = t[k][t[k].size() / 2];
+            if (k == 0 || med < best_us) {
+                best_us = med;
+                best = passed[k].second;
             }
         }
     } while (0);
