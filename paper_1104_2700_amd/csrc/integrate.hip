@@ -24,12 +24,62 @@ __device__ __forceinline__ int64_t next_time(const int64_t* t, const int64_t* dt
     return i < n ? e : INT64_MAX;
 }
 
+// Block-wide (kWG threads) minimum / sum / exclusive scan by wave shuffles
+// and one round through LDS (s: kWG/64 entries); every thread calls and
+// every thread gets the result.  A tree through LDS would take two barriers
+// per level.
+__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* s)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    __syncthreads();                     // s may still be read by a previous call
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t r = s[0];
+    for (int w = 1; w < kWG / 64; ++w) r = s[w] < r ? s[w] : r;
+    return r;
+}
+
+__device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* s)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int32_t r = 0;
+    for (int w = 0; w < kWG / 64; ++w) r += s[w];
+    return r;
+}
+
+// Exclusive prefix of v over the block's threads; *total gets the sum.
+__device__ __forceinline__ int32_t block_exscan_i32(int32_t v, int32_t* s, int32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    __syncthreads();
+    if (lane == 63) s[wave] = x;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+    for (int w = 0; w < kWG / 64; ++w) {
+        off += w < wave ? s[w] : 0;
+        tot += s[w];
+    }
+    *total = tot;
+    return off + x - v;
+}
+
 // Stage 1: per-block minimum of t_i + dt_i.
 __global__ void __launch_bounds__(kWG) sel_min_kernel(int64_t n, const int64_t* t,
                                                       const int64_t* dt,
                                                       int64_t* block_min)
 {
-    __shared__ int64_t sh[kWG];
+    __shared__ int64_t sh[kWG / 64];
     const int64_t base = (int64_t)blockIdx.x * kSelBlock;
     int64_t v = INT64_MAX;
 #pragma unroll
@@ -37,34 +87,15 @@ __global__ void __launch_bounds__(kWG) sel_min_kernel(int64_t n, const int64_t* 
         const int64_t e = next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x);
         v = e < v ? e : v;
     }
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            const int64_t o = sh[threadIdx.x + s];
-            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) block_min[blockIdx.x] = sh[0];
+    const int64_t bmin = block_min_i64(v, sh);
+    if (threadIdx.x == 0) block_min[blockIdx.x] = bmin;
 }
 
 __device__ int64_t block_min_all(const int64_t* block_min, int nb, int64_t* sh)
 {
     int64_t v = INT64_MAX;
     for (int b = threadIdx.x; b < nb; b += kWG) v = block_min[b] < v ? block_min[b] : v;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            const int64_t o = sh[threadIdx.x + s];
-            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
-        }
-        __syncthreads();
-    }
-    const int64_t T = sh[0];
-    __syncthreads();
-    return T;
+    return block_min_i64(v, sh);
 }
 
 // Stage 2: T from all block minima; count the active particles per block.
@@ -82,14 +113,9 @@ __global__ void __launch_bounds__(kWG) sel_count_kernel(int64_t n, const int64_t
 #pragma unroll
     for (int r = 0; r < kSelPer; ++r)
         c += next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x) == T ? 1 : 0;
-    shc[threadIdx.x] = c;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
-        __syncthreads();
-    }
+    const int32_t bcnt = block_sum_i32(c, shc);
     if (threadIdx.x == 0) {
-        block_cnt[blockIdx.x] = shc[0];
+        block_cnt[blockIdx.x] = bcnt;
         if (blockIdx.x == 0) *T_out = T;
     }
 }
@@ -115,27 +141,14 @@ __global__ void __launch_bounds__(kWG) sel_min_count_kernel(int64_t n, const int
         e[r] = next_time(t, dt, n, base + (int64_t)r * kWG + threadIdx.x);
         v = e[r] < v ? e[r] : v;
     }
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            const int64_t o = sh[threadIdx.x + s];
-            sh[threadIdx.x] = o < sh[threadIdx.x] ? o : sh[threadIdx.x];
-        }
-        __syncthreads();
-    }
-    const int64_t bmin = sh[0];
+    const int64_t bmin = block_min_i64(v, sh);
     int32_t c = 0;
+#pragma unroll
     for (int r = 0; r < kSelPer; ++r) c += (e[r] == bmin) ? 1 : 0;
-    shc[threadIdx.x] = c;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
-        __syncthreads();
-    }
+    const int32_t bcnt = block_sum_i32(c, shc);
     if (threadIdx.x == 0) {
         block_min[blockIdx.x] = bmin;
-        block_cnt[blockIdx.x] = shc[0];
+        block_cnt[blockIdx.x] = bcnt;
     }
     __threadfence();
     __syncthreads();
@@ -230,16 +243,6 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
                                   int C = 1, int32_t* act_start = nullptr,
                                   int32_t* act_cluster = nullptr)
 {
-    int32_t pre = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kWG) pre += block_cnt[b];
-    sh[threadIdx.x] = pre;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const int32_t off = sh[0];
-    __syncthreads();
     // this thread's particles are base + tid*kSelPer + r (contiguous per
     // thread so that a scan over threads keeps ascending order)
     const int64_t base = (int64_t)blockIdx.x * kSelBlock + (int64_t)threadIdx.x * kSelPer;
@@ -250,16 +253,11 @@ __device__ int32_t sel_write_body(int64_t n, const int64_t* t, const int64_t* dt
         f[r] = next_time(t, dt, n, base + r) == T;
         c += f[r] ? 1 : 0;
     }
-    sh[threadIdx.x] = c;
-    __syncthreads();
-    for (int d = 1; d < kWG; d <<= 1) {
-        const int32_t v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += v;
-        __syncthreads();
-    }
-    const int32_t pos = off + sh[threadIdx.x] - c;
-    const int32_t block_total = sh[kWG - 1];
+    int32_t pre = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kWG) pre += block_cnt[b];
+    const int32_t off = block_sum_i32(pre, sh);
+    int32_t block_total;
+    const int32_t pos = off + block_exscan_i32(c, sh + kWG / 64, &block_total);
     if (live) write_active(n, base, f, pos, idx, cl_off, C, act_start, act_cluster);
     __syncthreads();
     return off + block_total;
@@ -307,14 +305,9 @@ __global__ void __launch_bounds__(kWG) sel_write_plan_kernel(
     __threadfence();
     int32_t part = 0;
     for (int b = threadIdx.x; b < nb; b += kWG) part += block_cnt[b];
-    sh[threadIdx.x] = part;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
+    const int32_t total = block_sum_i32(part, sh);
     if (threadIdx.x == 0) {
-        const int32_t na = live ? sh[0] : 0;
+        const int32_t na = live ? total : 0;
         *n_act = na;
         count_step(counters, T, na);
         *ticket = 0u;
