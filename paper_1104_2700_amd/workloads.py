@@ -28,6 +28,8 @@ Names:
       FP64, mixed and FP32-jerk forces (the paper's Section 4 energy study)
   e4  whole-run speed against N (Plummer N = 1K .. 16K, eps = 4/N, t = 0 -> 1,
       FP64 and mixed): the paper's Section 5 performance sweep
+  o1  HBM bandwidth of the O(N) stages at large N (2^20 .. 2^24 particles):
+      standalone select, predict and correct (all particles active)
 
 Every run reports wall time, block steps, interactions, interactions/s,
 GFLOPS at the paper's 60 flops per interaction (Section 5), clamped steps
@@ -365,8 +367,74 @@ def e4(ctx, t_end=1.0, ns=(1024, 2048, 4096, 8192, 16384), seed=7, form="paper")
     return {"config": "plummer_speed_vs_n", "t_end": t_end, "dt_form": form, "rows": rows}
 
 
+def o1(ctx, ns=(1 << 20, 1 << 22, 1 << 24), reps=20, seed=8):
+    """Achieved HBM bandwidth of the O(N) stages, against the 8 TB/s peak.
+    The state is synthetic (uniform positions and velocities, small a and j,
+    t = 0, every dt = 2^-10): the stages' cost does not depend on the
+    physics.  Bytes per particle, counted from the kernels' loads and stores:
+    select 3 x 16 B read (t, dt in the minimum, count and write passes) +
+    4 B written (idx); predict 104 B read (x, v, a, j, t) + 48 B written
+    (xp, vp); correct (every particle active) 164 B read (idx, dt, xp, vp,
+    a, j and the new acc, jerk, pot) + 120 B written (x, v, a, j, pot, t,
+    dt)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    rows = []
+    for n in ns:
+        f64 = dict(dtype=torch.float64, device="cuda")
+        s = H.State(torch.zeros(3, n, **f64), torch.zeros(3, n, **f64),
+                    torch.full((n,), 1.0 / n, **f64), TB)
+        for t_ in (s.x, s.v):
+            t_.uniform_(-1.0, 1.0, generator=g)
+        for t_ in (s.a, s.j):
+            t_.uniform_(-1e-3, 1e-3, generator=g)
+        s.dt.fill_(1 << (TB - 10))
+        idx = torch.empty(n, dtype=torch.int32, device="cuda")
+        na = torch.empty(1, dtype=torch.int32, device="cuda")
+        T = torch.empty(1, dtype=torch.int64, device="cuda")
+        acc = s.a.clone()
+        jrk = s.j.clone()
+        pot = torch.zeros(n, **f64)
+        p = _params(0.02)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps * 1e-3
+
+        t_sel = timed(lambda: ctx.select_block(s, idx, na, T))
+        t_pred = timed(lambda: ctx.predict(s, T_host=1 << (TB - 10)))
+
+        def corr():
+            # every particle active at T = dt (the state is reset each time)
+            s.t.zero_()
+            s.dt.fill_(1 << (TB - 10))
+            ctx.correct(s, idx, acc, jrk, pot, p, T_host=1 << (TB - 10), n_act_max=n)
+        t_fill = timed(lambda: (s.t.zero_(), s.dt.fill_(1 << (TB - 10))))
+        t_corr = timed(corr) - t_fill
+        row = {"n": n}
+        for name, sec, byt in (("select", t_sel, 52), ("predict", t_pred, 152),
+                               ("correct", t_corr, 284)):
+            row[name] = {"us": sec * 1e6, "bytes_per_particle": byt,
+                         "GB_per_s": byt * n / sec / 1e9,
+                         "frac_of_8TBps": byt * n / sec / 8e12}
+        rows.append(row)
+        _log("  o1 N %9d  select %.0f GB/s  predict %.0f GB/s  correct %.0f GB/s"
+             % (n, row["select"]["GB_per_s"], row["predict"]["GB_per_s"],
+                row["correct"]["GB_per_s"]))
+        del s, idx, acc, jrk, pot
+        torch.cuda.empty_cache()
+    return {"config": "o_n_stages_bandwidth", "rows": rows}
+
+
 RUNNERS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "e1": e1, "e2": e2, "e3": e3,
-           "e4": e4}
+           "e4": e4, "o1": o1}
 
 
 def main(argv=None):
