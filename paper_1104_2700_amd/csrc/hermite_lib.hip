@@ -260,8 +260,10 @@ int ensure_step_scratch(hermite_ctx* c, int64_t n)
     return HERMITE_OK;
 }
 
-// One block step on stream st using the context's step scratch: fused
-// select + predict + plan, the persistent sweep, fused reduce + correct.
+// One block step on stream st using the context's step scratch: selection
+// with the sweep plan (two kernels; one up to 4096 particles; or inside
+// the sweep for one system of up to kFusedSelMax), the persistent sweep
+// (predicting the particles it reads), and the fused reduce + correct.
 int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                  double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
                  hipStream_t st)
@@ -777,8 +779,9 @@ int hermite_set_tuning(hermite_ctx* c, int precision, const hermite_tuning* in)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Autotuner: times candidate launch shapes with HIP events and keeps the
-// fastest one whose output agrees with the default shape.
+// Autotuner: times candidate launch shapes with HIP events (a screen, then
+// interleaved re-timing of the fastest) and keeps the fastest one whose
+// output stays within the precision's tolerance of an FP64 sweep.
 // ---------------------------------------------------------------------------
 namespace {
 
