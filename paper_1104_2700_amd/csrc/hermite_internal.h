@@ -101,7 +101,8 @@ inline int reduce_grid(int64_t n_act_max)
     return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
 }
 
-// Sweep launchers (sweep.hip).  precision: 0 fp64, 1 mixed, 2 mixed-2f.
+// Sweep launchers (sweep.hip).  precision: 0 fp64, 1 mixed, 2 mixed-2f,
+// 3 mixed with FP32 velocities and jerk sums.
 // variant bit 0: two active particles per lane (else one); bit 1: split
 // FP32 hi/lo differences in the mixed precisions.
 // pot_only: the energy sweep (FP64, potential only).

@@ -47,7 +47,6 @@ namespace hm {
 namespace {
 
 constexpr int kMixedK = 16;   // FP32 run length before an FP64 flush
-constexpr int64_t kDirectMinJ = 1024;   // shortest j-chunk read without LDS
 
 __device__ __forceinline__ double rsqrt_f64(double s)
 {
@@ -443,59 +442,6 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[7])
     out[6] = -S.pp.value();
 }
 
-// Direct mode, used when a whole wave shares each active particle
-// (L = 64, tiny active blocks): lane l takes j = j0 + l, j0 + l + 64, ...
-// straight from global memory (coalesced, L2-resident), so there is no LDS
-// staging and no barrier in the loop; only latency matters in this regime.
-template <int PREC, int IPL, typename RUN>
-__device__ __forceinline__ void direct_loop(const SweepArgs& a, int64_t j0, int64_t j1,
-                                            int lane, const int (&ii)[IPL],
-                                            const I64 (&I)[IPL], double eps2,
-                                            SumF (&F)[IPL], RUN (&S)[IPL])
-{
-    const float eps2f = (float)eps2;
-    const int64_t T = a.pred_x ? *a.pred_T : 0;
-    int run = 0;
-    for (int64_t jj = j0 + lane; jj < j1; jj += 64) {
-        double r[3], w[3];
-        fetch_particle(a, jj, T, r, w);
-        const double xj = r[0], yj = r[1], zj = r[2];
-        const double vxj = w[0], vyj = w[1], vzj = w[2];
-        const double mj = a.m[jj];
-#pragma unroll
-        for (int q = 0; q < IPL; ++q) {
-            const bool self = jj == (int64_t)ii[q];
-            if constexpr (PREC == 0) {
-                pair_f64<true>(I[q], eps2, xj, yj, zj, vxj, vyj, vzj, mj, self, S[q]);
-            } else if constexpr (PREC == 3) {
-                I64SP Is{I[q].x, I[q].y, I[q].z, (float)I[q].vx, (float)I[q].vy,
-                         (float)I[q].vz};
-                pair_sp<true>(Is, eps2f, xj, yj, zj, (float)vxj, (float)vyj, (float)vzj,
-                              (float)mj, self, F[q]);
-            } else {
-                pair_mixed<true>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, (float)mj, self,
-                                 F[q]);
-            }
-        }
-        if constexpr (PREC != 0) {
-            if (++run == kMixedK) {
-                run = 0;
-#pragma unroll
-                for (int q = 0; q < IPL; ++q) {
-                    if constexpr (PREC == 3) flush_keep_jerk(F[q], S[q]);
-                    else flush(F[q], S[q]);
-                }
-            }
-        }
-    }
-    if constexpr (PREC != 0) {
-#pragma unroll
-        for (int q = 0; q < IPL; ++q) {
-            if constexpr (PREC == 3) flush_keep_jerk(F[q], S[q]);
-            else flush(F[q], S[q]);
-        }
-    }
-}
 
 // ------------------------------------------------------------------------
 // The persistent sweep kernel.
@@ -638,18 +584,11 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
             F[q].zero();
         }
 
-        // A whole wave per particle and a long chunk: lanes read consecutive
-        // j straight from global memory (no LDS, no barrier).  Short chunks
-        // go through LDS, where one cooperative tile load replaces a round
-        // trip per j and lane.
-        const bool direct = !POT_ONLY && L == 64 && jc >= kDirectMinJ;
-        if constexpr (!POT_ONLY) {
-            if (direct) {
-                // wave-uniform: every lane of the wave serves the same particles
-                direct_loop<PREC, IPL>(a, j0, j1, sub, ii, I, eps2, F, S);
-            }
-        }
-        for (int64_t tb = j0; tb < j1 && !direct; tb += kTJ) {
+        // j streams through LDS in tiles of kTJ: one cooperative load per
+        // tile (a lane reading its own j from global memory instead waits a
+        // round trip per j, which measured slower whenever L = 64 chunks
+        // were long)
+        for (int64_t tb = j0; tb < j1; tb += kTJ) {
             const int cnt = (int)((j1 - tb) < kTJ ? (j1 - tb) : kTJ);
             __syncthreads();
             if (tid < cnt) {
