@@ -179,6 +179,43 @@ hipError_t launch_select_sweep(const SweepArgs& a, int precision, int variant, i
 
 hipError_t launch_sweep_only(const SweepArgs& a, int precision, int variant, int grid,
                              hipStream_t st);
+
+// Step-size structure of a block-step run.  Every t_i is a multiple of its
+// power-of-two step dt_i and t_i <= T_last < t_i + dt_i (T_last: the last
+// block time), so particle i's next time is the first multiple of dt_i
+// after T_last.  The next block time is then the first multiple of the
+// smallest occupied step after T_last, and the active block is every
+// particle whose step divides it: with the particles ordered by step size
+// (perm), a prefix of perm.  The corrector gives every active particle a
+// step that divides the block time, so re-sorting that prefix by the new
+// steps keeps the whole order; selection costs O(n_act) instead of O(n).
+struct LevelArgs {
+    int64_t n;
+    const int64_t* t;
+    const int64_t* dt;
+    int64_t dt_floor;    // smallest step the corrector can give, 2^(tick_bits - k_max)
+    int32_t* perm;       // [n] particle ids by step size, smallest first
+    int32_t* cnt;        // [64] particles with dt = 2^b ticks
+    int32_t* cursor;     // [64] (building the order)
+    int64_t* misc;       // [0] T_last; [1] max t, [2] min t + dt, [3] inconsistent (checks)
+    int32_t* tmp;        // [n] re-sort scratch for blocks beyond the LDS staging
+    int64_t T_end;
+    int32_t* na;         // n_act: the previous step's in, this step's out
+    int64_t* T;          // block time: the previous step's in, this step's out
+    int32_t* idx;        // [n] active list grouped by cluster (C > 1)
+    int64_t* counters;
+};
+
+// Counts the steps of a state and checks that it is one the block scheme
+// can have produced (misc[1..3]); misc and cnt must hold {0, INT64_MIN,
+// INT64_MAX, 0} and zeros.  launch_level_build then orders the particles
+// (cursor zeroed) and sets T_last = max t and *na = 0.
+hipError_t launch_level_count(const LevelArgs& L, hipStream_t st);
+hipError_t launch_level_build(const LevelArgs& L, hipStream_t st);
+// One workgroup: re-sorts the previous block by its new steps, selects the
+// next block, groups it by cluster (C > 1; C <= kLdsClusters) and plans
+// the sweep.
+hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st);
 hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);
 
 hipError_t launch_init_dt(int64_t n, int tick_bits, const double* a,

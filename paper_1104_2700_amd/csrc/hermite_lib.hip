@@ -74,6 +74,8 @@ struct hermite_ctx {
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
+    // step-size order of a run (hermite_run)
+    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc;
     std::vector<GraphEntry> graphs;
     // grid of the fused select + sweep for the last shape it was sized for
     struct {
@@ -260,13 +262,64 @@ int ensure_step_scratch(hermite_ctx* c, int64_t n)
     return HERMITE_OK;
 }
 
+LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* p,
+                     int64_t T_end)
+{
+    LevelArgs L;
+    std::memset(&L, 0, sizeof L);
+    L.n = s->n;
+    L.t = s->t;
+    L.dt = s->dt;
+    L.dt_floor = ((int64_t)1) << (s->tick_bits - p->k_max);
+    L.perm = (int32_t*)c->lvl_perm.p;
+    L.cnt = (int32_t*)c->lvl_cnt.p;
+    L.cursor = (int32_t*)c->lvl_cursor.p;
+    L.misc = (int64_t*)c->lvl_misc.p;
+    L.tmp = (int32_t*)c->lvl_tmp.p;
+    L.T_end = T_end;
+    L.na = (int32_t*)c->step_na.p;
+    L.T = (int64_t*)c->step_T.p;
+    L.idx = (int32_t*)c->step_idx.p;
+    L.counters = (int64_t*)c->counters.p;
+    return L;
+}
+
+// Builds the step-size order of s for a run (synchronises st).  *ok is
+// false when the state is not one the block scheme can have produced (the
+// run then selects every block from t and dt).
+int level_init(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* p,
+               hipStream_t st, bool* ok)
+{
+    *ok = false;
+    CHECK(ensure(c, c->lvl_perm, sizeof(int32_t) * s->n));
+    CHECK(ensure(c, c->lvl_tmp, sizeof(int32_t) * s->n));
+    CHECK(ensure(c, c->lvl_cnt, sizeof(int32_t) * 64));
+    CHECK(ensure(c, c->lvl_cursor, sizeof(int32_t) * 64));
+    CHECK(ensure(c, c->lvl_misc, sizeof(int64_t) * 4));
+    const LevelArgs L = level_args(c, s, p, 0);
+    const int64_t init[4] = {0, INT64_MIN, INT64_MAX, 0};
+    HIP_OK(hipMemcpyAsync(L.misc, init, sizeof init, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * 64, st));
+    HIP_OK(hipMemsetAsync(L.cursor, 0, sizeof(int32_t) * 64, st));
+    HIP_OK(launch_level_count(L, st));
+    int64_t h[4];
+    HIP_OK(hipMemcpyAsync(h, L.misc, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (h[3] != 0 || h[1] >= h[2]) return HERMITE_OK;
+    HIP_OK(launch_level_build(L, st));
+    *ok = true;
+    return HERMITE_OK;
+}
+
 // One block step on stream st using the context's step scratch: selection
-// with the sweep plan (two kernels; one up to 4096 particles; or inside
-// the sweep for one system of up to kFusedSelMax), the persistent sweep
-// (predicting the particles it reads), and the fused reduce + correct.
+// with the sweep plan (from the step-size order in a run, one kernel;
+// otherwise from t and dt: two kernels, one up to 4096 particles, or
+// inside the sweep for one system of up to kFusedSelMax), the persistent
+// sweep (predicting the particles it reads), and the fused reduce +
+// correct.
 int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                  double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
-                 hipStream_t st)
+                 bool level, hipStream_t st)
 {
     const int64_t n = s->n;
     int32_t* idx = (int32_t*)c->step_idx.p;
@@ -274,9 +327,11 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     int64_t* T = (int64_t*)c->step_T.p;
     double* out = (double*)c->step_out.p;
     int64_t* counters = (int64_t*)c->counters.p;
+    // one system in a run: the active block is the prefix of the order
+    int32_t* aidx = (level && !cl) ? (int32_t*)c->lvl_perm.p : idx;
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[precision];
-    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, na, (int32_t)n, eps2, tu, out,
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, aidx, na, (int32_t)n, eps2, tu, out,
                         out + 3 * n, out + 6 * n, &a));
     a.ipl = (tu.variant & 1) ? 2 : 1;
     // with clusters the selection records the active runs and clusters
@@ -292,7 +347,10 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     a.pred_T = T;
     a.tick = std::ldexp(1.0, -s->tick_bits);
     const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
-    if (!cl && n <= kFusedSelMax) {
+    if (level) {
+        HIP_OK(launch_level_select(level_args(c, s, p, T_end), a, st));
+        HIP_OK(launch_sweep_only(a, precision, tu.variant, grid, st));
+    } else if (!cl && n <= kFusedSelMax) {
         // one small system: every sweep workgroup selects the block itself
         // (no selection kernel); the grid is capped at the most items any
         // active count can give, so idle workgroups do no selection
@@ -322,7 +380,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     std::memset(&ca, 0, sizeof ca);
     ca.n = n;
     ca.tick_bits = s->tick_bits;
-    ca.idx = idx;
+    ca.idx = aidx;
     ca.n_act_dev = na;
     ca.n_act_max = (int32_t)n;
     ca.T_dev = T;
@@ -587,18 +645,19 @@ int hermite_energy(hermite_ctx* c, const hermite_state* s, const hermite_cluster
 // once as one graph (keyed by the step parameters and K) and replayed.
 static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                         double eps2, int precision, const hermite_dt_params* p,
-                        int64_t T_end, int use_graph, int K, void* stream);
+                        int64_t T_end, int use_graph, int K, bool level, void* stream);
 
 int hermite_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                  double eps2, int precision, const hermite_dt_params* p, int64_t T_end,
                  int use_graph, void* stream)
 {
-    return launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, stream);
+    return launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, false, stream);
 }
 
+// level: select from the step-size order built by level_init (hermite_run).
 static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                         double eps2, int precision, const hermite_dt_params* p,
-                        int64_t T_end, int use_graph, int K, void* stream)
+                        int64_t T_end, int use_graph, int K, bool level, void* stream)
 {
     CHECK(check_ctx(c));
     CHECK(check_state(s));
@@ -617,12 +676,13 @@ static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_cl
     }
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) {
-        for (int k = 0; k < K; ++k) CHECK(enqueue_step(c, s, cl, eps2, precision, p, T_end, st));
+        for (int k = 0; k < K; ++k)
+            CHECK(enqueue_step(c, s, cl, eps2, precision, p, T_end, level, st));
         return HERMITE_OK;
     }
 
     const std::string key = step_key(s, cl, eps2, precision, p, T_end, c->tuning[precision]) +
-                            "|K" + std::to_string(K);
+                            "|K" + std::to_string(K) + (level ? "|L" : "");
     GraphEntry* g = nullptr;
     for (auto& e : c->graphs)
         if (e.key == key) g = &e;
@@ -638,7 +698,7 @@ static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_cl
         HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         int rc = HERMITE_OK;
         for (int k = 0; k < K && rc == HERMITE_OK; ++k)
-            rc = enqueue_step(c, s, cl, eps2, precision, p, T_end, c->cap_stream);
+            rc = enqueue_step(c, s, cl, eps2, precision, p, T_end, level, c->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
         if (rc != HERMITE_OK) {
@@ -721,6 +781,14 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
     hipStream_t st = (hipStream_t)stream;
     int64_t c0[5], c1[5];
     CHECK(hermite_counters(c, c0, stream));
+    // Select from the step-size order unless the sweep selects itself (one
+    // small system) or the clusters do not fit the selection's LDS tables.
+    bool level = false;
+    if (!(cl == nullptr && s->n <= kFusedSelMax) && (!cl || cl->n_clusters <= kLdsClusters)) {
+        CHECK(check_clusters(cl, s->n));
+        CHECK(ensure_step_scratch(c, s->n));
+        CHECK(level_init(c, s, p, st, &level));
+    }
     int64_t launched = 0;
     int32_t done = 0;
     for (;;) {
@@ -729,9 +797,10 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
         int k = 0;
         for (; k + kRunGraphSteps <= batch; k += kRunGraphSteps)
             CHECK(launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, kRunGraphSteps,
-                               stream));
+                               level, stream));
         for (; k < batch; ++k)
-            CHECK(launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, stream));
+            CHECK(launch_steps(c, s, cl, eps2, precision, p, T_end, use_graph, 1, level,
+                               stream));
         launched += batch;
         int64_t T = 0;
         int32_t na = 0;

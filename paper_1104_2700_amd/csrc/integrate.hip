@@ -384,6 +384,228 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
     plan_body(sa, na);
 }
 
+// ---- block selection from the step-size order (procedure step 1) ---------
+__device__ __forceinline__ int log2_step(int64_t dt)
+{
+    return 63 - __clzll((unsigned long long)dt);
+}
+
+// Step counts of the state and its consistency: every dt_i a power of two
+// no finer than dt_floor, t_i >= 0 a multiple of dt_i, and (checked on the
+// host) max t < min (t + dt).
+__global__ void __launch_bounds__(kWG) level_count_kernel(LevelArgs L)
+{
+    __shared__ int32_t h[64];
+    __shared__ int64_t s1[kWG / 64];
+    __shared__ int32_t s2[kWG / 64];
+    const int tid = threadIdx.x;
+    if (tid < 64) h[tid] = 0;
+    __syncthreads();
+    int64_t tmax = INT64_MIN, nmin = INT64_MAX;
+    int32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < L.n; i += (int64_t)gridDim.x * kWG) {
+        const int64_t ti = L.t[i], di = L.dt[i];
+        if (di < L.dt_floor || (di & (di - 1)) != 0 || ti < 0 || (ti & (di - 1)) != 0 ||
+            ti > INT64_MAX - di) {
+            bad = 1;
+        } else {
+            atomicAdd(&h[log2_step(di)], 1);
+            nmin = ti + di < nmin ? ti + di : nmin;
+        }
+        tmax = ti > tmax ? ti : tmax;
+    }
+    nmin = block_min_i64(nmin, s1);
+    tmax = ~block_min_i64(~tmax, s1);            // ~ reverses the order without overflow
+    bad = block_sum_i32(bad, s2);
+    if (tid == 0) {
+        __hip_atomic_fetch_max(&L.misc[1], tmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_min(&L.misc[2], nmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bad) __hip_atomic_fetch_max(&L.misc[3], (int64_t)1, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < 64 && h[tid] > 0) atomicAdd(&L.cnt[tid], h[tid]);
+}
+
+// Orders the particles by step size (a counting sort; the order within one
+// step size is unspecified).
+__global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
+{
+    __shared__ int32_t h[64], base[64];
+    const int tid = threadIdx.x;
+    if (tid < 64) h[tid] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < L.n; i += (int64_t)gridDim.x * kWG)
+        atomicAdd(&h[log2_step(L.dt[i])], 1);
+    __syncthreads();
+    if (tid < 64) {
+        // this block's place in every step size: the sizes before it, then
+        // the blocks that claimed that size before it
+        const int32_t c = L.cnt[tid];
+        int32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(x, o);
+            if (tid >= o) x += u;
+        }
+        const int32_t mine = h[tid];
+        base[tid] = x - c + (mine > 0 ? atomicAdd(&L.cursor[tid], mine) : 0);
+        h[tid] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < L.n; i += (int64_t)gridDim.x * kWG) {
+        const int b = log2_step(L.dt[i]);
+        L.perm[base[b] + atomicAdd(&h[b], 1)] = (int32_t)i;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        L.misc[0] = L.misc[1];
+        *L.na = 0;
+    }
+}
+
+constexpr int kLevelLds = 2048;   // blocks re-sorted in LDS (larger ones via L.tmp)
+
+__global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArgs sa)
+{
+    __shared__ int32_t s_hist[64], s_cur[64], s_cnt[64];
+    __shared__ int32_t s_id[kLevelLds];
+    __shared__ int32_t s_aux[kLevelLds];
+    __shared__ uint8_t s_lv[kLevelLds];
+    __shared__ int32_t s_scan[kWG / 64];
+    __shared__ int32_t s_na;
+    const int tid = threadIdx.x;
+    const int32_t na_prev = *L.na;
+    const int64_t T_prev = *L.T;
+    int64_t Tlast = L.misc[0];
+    if (tid < 64) {
+        s_hist[tid] = 0;
+        s_cnt[tid] = L.cnt[tid];
+    }
+    __syncthreads();
+
+    // 1. the previous block, ordered by the steps the corrector gave it
+    if (na_prev > 0) {
+        Tlast = T_prev;
+        const bool lds = na_prev <= kLevelLds;
+        for (int p = tid; p < na_prev; p += kWG) {
+            const int32_t i = L.perm[p];
+            const int b = log2_step(L.dt[i]);
+            if (lds) {
+                s_id[p] = i;
+                s_lv[p] = (uint8_t)b;
+            }
+            atomicAdd(&s_hist[b], 1);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // every particle whose step divides T_prev was in that block
+            const int z = __builtin_ctzll((unsigned long long)T_prev);
+            const int32_t hb = s_hist[tid];
+            s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + hb;
+            int32_t x = hb;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(x, o);
+                if (tid >= o) x += u;
+            }
+            s_cur[tid] = x - hb;
+        }
+        __syncthreads();
+        int32_t* out = lds ? s_aux : L.tmp;
+        for (int p = tid; p < na_prev; p += kWG) {
+            int32_t i;
+            int b;
+            if (lds) {
+                i = s_id[p];
+                b = s_lv[p];
+            } else {
+                i = L.perm[p];
+                b = log2_step(L.dt[i]);
+            }
+            out[atomicAdd(&s_cur[b], 1)] = i;
+        }
+        __syncthreads();
+        for (int p = tid; p < na_prev; p += kWG) L.perm[p] = out[p];
+        if (tid < 64) L.cnt[tid] = s_cnt[tid];
+        if (tid == 0) L.misc[0] = Tlast;
+        __syncthreads();
+    }
+
+    // 2. next block time and active count (wave 0, one lane per step size)
+    if (tid < 64) {
+        const int32_t c = s_cnt[tid];
+        const unsigned long long occ = __ballot(c > 0);
+        int64_t Tn = INT64_MAX;
+        int32_t na = 0;
+        if (occ != 0ull) {
+            const int bmin = __builtin_ctzll(occ);
+            Tn = ((Tlast >> bmin) + 1) << bmin;
+            const int z = __builtin_ctzll((unsigned long long)Tn);
+            int32_t v = tid <= z ? c : 0;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            na = v;
+        }
+        if (Tn > L.T_end) na = 0;
+        if (tid == 0) {
+            s_na = na;
+            *L.T = Tn;
+            *L.na = na;
+            count_step(L.counters, Tn, na);
+        }
+    }
+    __syncthreads();
+    const int32_t na = s_na;
+
+    // 3. with clusters: the block grouped by cluster (counting sort), with
+    // every cluster's first position and every position's cluster
+    const int C = sa.n_clusters;
+    if (C > 1 && na > 0) {
+        __shared__ int64_t s_off[kLdsClusters + 1];
+        __shared__ int32_t s_ch[kLdsClusters];
+        for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
+        for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
+        __syncthreads();
+        const bool lds = na <= kLevelLds;
+        for (int p = tid; p < na; p += kWG) {
+            const int32_t i = L.perm[p];
+            const int c = upper_bound_i64(s_off, C + 1, (int64_t)i) - 1;
+            if (lds) {
+                s_id[p] = i;
+                s_aux[p] = c;
+            }
+            atomicAdd(&s_ch[c], 1);
+        }
+        __syncthreads();
+        const int per = (C + kWG - 1) / kWG;
+        const int c0 = tid * per < C ? tid * per : C;
+        const int c1 = c0 + per < C ? c0 + per : C;
+        int32_t loc = 0;
+        for (int c = c0; c < c1; ++c) loc += s_ch[c];
+        int32_t tot;
+        int32_t run = block_exscan_i32(loc, s_scan, &tot);
+        for (int c = c0; c < c1; ++c) {
+            const int32_t k = s_ch[c];
+            s_ch[c] = run;
+            sa.act_start[c] = run;
+            run += k;
+        }
+        __syncthreads();
+        for (int p = tid; p < na; p += kWG) {
+            int32_t i;
+            int c;
+            if (lds) {
+                i = s_id[p];
+                c = s_aux[p];
+            } else {
+                i = L.perm[p];
+                c = upper_bound_i64(s_off, C + 1, (int64_t)i) - 1;
+            }
+            const int32_t pos = atomicAdd(&s_ch[c], 1);
+            L.idx[pos] = i;
+            sa.act_cluster[pos] = c;
+        }
+        __syncthreads();
+    }
+    plan_body(sa, na);
+}
+
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
 __global__ void __launch_bounds__(kWG) predict_kernel(int64_t n, const int64_t* __restrict__ t,
                                                       const int64_t* T_dev, int64_t T_host,
@@ -423,11 +645,6 @@ __device__ int64_t quantize_dt(double crit, int k_old, int64_t T, int tick_bits,
     if (k_old >= 0 && k < k_old - 1) k = k_old - 1;
     while (k < k_max && (T & ((((int64_t)1) << (tick_bits - k)) - 1)) != 0) ++k;
     return ((int64_t)1) << (tick_bits - k);
-}
-
-__device__ __forceinline__ int log2_ticks(int64_t dt)
-{
-    return 63 - __clzll((unsigned long long)dt);
 }
 
 // ---- corrector + next step (procedure steps 5-8) -------------------------
@@ -483,7 +700,7 @@ __device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double
     const double R = (A * S + J * J) / (J * Cn + S * S);
     const double crit = c.form == 0 ? c.eta * sqrt(R) : sqrt(c.eta * R);
     if (c.crit_out) c.crit_out[p] = crit;
-    const int k_old = c.tick_bits - log2_ticks(dt_old);
+    const int k_old = c.tick_bits - log2_step(dt_old);
     int cl;
     c.dt[i] = quantize_dt(crit, k_old, T, c.tick_bits, c.k_min, c.k_max, &cl);
     if (cl && c.counters) atomicAdd((unsigned long long*)&c.counters[2], 1ull);
@@ -654,6 +871,30 @@ hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, in
     hipLaunchKernelGGL(sel_write_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
                        (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
                        counters, sa, ticket);
+    return hipGetLastError();
+}
+
+static int level_grid(int64_t n)
+{
+    const int g = nblocks(n, kWG * 8);
+    return g < 1 ? 1 : (g > 2048 ? 2048 : g);
+}
+
+hipError_t launch_level_count(const LevelArgs& L, hipStream_t st)
+{
+    hipLaunchKernelGGL(level_count_kernel, dim3(level_grid(L.n)), dim3(kWG), 0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_build(const LevelArgs& L, hipStream_t st)
+{
+    hipLaunchKernelGGL(level_build_kernel, dim3(level_grid(L.n)), dim3(kWG), 0, st, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st)
+{
+    hipLaunchKernelGGL(level_select_kernel, dim3(1), dim3(kWG), 0, st, L, sa);
     return hipGetLastError();
 }
 

@@ -441,6 +441,157 @@ def test_ensemble_multiblock_lockstep(H, ctx, sizes):
             assert np.array_equal(g["t"][lo:hi], sub["t"])
 
 
+def _ensemble(H, sizes, seed0=700):
+    from paper_1104_2700_amd import inputs
+    xs, vs, ms = [], [], []
+    for c, nc in enumerate(sizes):
+        x, v, m = inputs.plummer(nc, seed0 + c)
+        xs.append(x); vs.append(v); ms.append(m)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps2 = (4.0 / np.maximum(np.array(sizes, float), 64)) ** 2
+    return (np.concatenate(xs, 1), np.concatenate(vs, 1), np.concatenate(ms),
+            H.Clusters(off, eps2))
+
+
+def _run_vs_steps(H, ctx, s0, eps2, params, prec, K, clusters=None, T_end=1 << (TB - 3),
+                  sync_every=16):
+    """K steps by hermite_run (selection from the step-size order) and by K
+    hermite_step calls (selection from t and dt): same state bit for bit,
+    same counters and block-size histogram."""
+    sa, sb = s0.clone(), s0.clone()
+    c0, h0 = ctx.counters(), ctx.block_histogram()
+    st, it = ctx.run(sa, eps2, params, T_end, prec, use_graph=True, sync_every=sync_every,
+                     max_steps=K, clusters=clusters)
+    c1, h1 = ctx.counters(), ctx.block_histogram()
+    for k in range(K):
+        ctx.step(sb, eps2, params, prec, T_end=T_end, use_graph=(k % 3 == 0), clusters=clusters)
+    c2, h2 = ctx.counters(), ctx.block_histogram()
+    torch.cuda.synchronize()
+    assert st == c1["steps"] - c0["steps"] == c2["steps"] - c1["steps"]
+    assert it == c1["interactions"] - c0["interactions"] == c2["interactions"] - c1["interactions"]
+    assert c1["clamped"] - c0["clamped"] == c2["clamped"] - c1["clamped"]
+    assert [b - a for a, b in zip(h0, h1)] == [b - a for a, b in zip(h1, h2)]
+    for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+        assert torch.equal(getattr(sa, key), getattr(sb, key)), key
+    return st, sa
+
+
+@pytest.mark.parametrize("n,prec", [(3000, 0), (6000, 1), (20000, 0)])
+def test_run_order_selection_matches_steps(H, ctx, n, prec):
+    """Block steps selected from the step-size order (hermite_run) give the
+    state of steps selected from t and dt (hermite_step), for one selection
+    workgroup (n = 3000) and several (n = 6000, 20000), over several run
+    batches (each batch's graph replays and syncs in between)."""
+    x, v, m, _ = _c1_setup(H, n=n, seed=41)
+    eps2 = (4.0 / n) ** 2
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, prec)
+    st, _ = _run_vs_steps(H, ctx, s0, eps2, params, prec, 45, sync_every=13)
+    assert st == 45
+
+
+@pytest.mark.parametrize("clustered", [False, True], ids=["one", "clusters"])
+def test_run_order_selection_whole_blocks(H, ctx, clustered):
+    """Every particle on one shared step at t = 0: the first block is the
+    whole system (6000 / 6265 particles), larger than the selection's LDS
+    staging, so the next step re-sorts (and groups by cluster) through
+    global memory; the state still follows hermite_step bit for bit."""
+    if clustered:
+        x, v, m, cl = _ensemble(H, [3000, 1, 2500, 700, 64])
+        eps2 = 0.0
+    else:
+        x, v, m, _ = _c1_setup(H, n=6000, seed=43)
+        cl, eps2 = None, (4.0 / 6000) ** 2
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, H.FP64, clusters=cl)
+    s0.dt.fill_(1 << (TB - 12))
+    s0.t.zero_()
+    s1 = s0.clone()
+    ctx.run(s1, eps2, params, 1 << (TB - 3), H.FP64, max_steps=1, clusters=cl)
+    assert ctx.counters()["n_act"] == s0.n
+    _run_vs_steps(H, ctx, s0, eps2, params, H.FP64, 24, clusters=cl)
+
+
+@pytest.mark.parametrize("sizes", [[9000, 1, 8000, 2500, 700], [300] * 40],
+                         ids=["n20201", "c40"])
+def test_run_order_selection_ensemble(H, ctx, sizes):
+    """Ensembles: the block grouped by cluster from the step-size order
+    gives the state of the selection from t and dt."""
+    x, v, m, cl = _ensemble(H, sizes, seed0=900)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, 0.0, params, H.MIXED, clusters=cl)
+    _run_vs_steps(H, ctx, s0, 0.0, params, H.MIXED, 40, clusters=cl)
+
+
+@pytest.mark.parametrize("case", ["t_off_grid", "dt_not_pow2", "dt_below_floor", "overdue"])
+def test_run_inconsistent_state_falls_back(H, ctx, case):
+    """A state the block scheme cannot have produced (a time off its step's
+    grid, a step that is not a power of two or is finer than 2^-k_max, a
+    particle due before the last block time) is run with the selection from
+    t and dt: the result equals hermite_step's."""
+    n = 5000
+    x, v, m, _ = _c1_setup(H, n=n, seed=47)
+    eps2 = (4.0 / n) ** 2
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 18)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    g = s0.to_numpy()
+    t, dt = g["t"].copy(), g["dt"].copy()
+    if case == "t_off_grid":
+        t[17] = 1
+    elif case == "dt_not_pow2":
+        dt[17] = 3 * (1 << 6)
+    elif case == "dt_below_floor":
+        dt[17] = 1
+    else:
+        # particle 17 at t = 2 dt with its next time before another's t
+        t[:] = 0
+        dt[:] = 1 << (TB - 8)
+        t[18] = 4 * dt[18]
+        t[17] = 0
+    s0.t.copy_(_dev(t))
+    s0.dt.copy_(_dev(dt))
+    torch.cuda.synchronize()
+    _run_vs_steps(H, ctx, s0, eps2, params, H.FP64, 20)
+
+
+def test_run_order_selection_to_the_end(H, ctx):
+    """A run to T_end through the step-size order (n = 3000, several calls)
+    ends with every particle at T_end, then steps change nothing; the same
+    run of hermite_step calls gives the same state."""
+    n = 3000
+    x, v, m, _ = _c1_setup(H, n=n, seed=49)
+    eps2 = (4.0 / n) ** 2
+    params = H.dt_params(0.05, H.DT_AARSETH, 6, 14)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, H.FP64)
+    T_end = 1 << (TB - 6)       # one coarsest step
+    sa = s0.clone()
+    total = calls = 0
+    while True:
+        st, it, done = ctx.run(sa, eps2, params, T_end, H.FP64, sync_every=3, max_steps=7,
+                               with_done=True)
+        total += st
+        calls += 1
+        if done:
+            break
+    torch.cuda.synchronize()
+    g = sa.to_numpy()
+    assert np.all(g["t"] == T_end) and total > 20 and calls > 3
+    sb = s0.clone()
+    for k in range(total + 5):
+        ctx.step(sb, eps2, params, H.FP64, T_end=T_end, use_graph=(k % 2 == 0))
+    torch.cuda.synchronize()
+    for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+        assert torch.equal(getattr(sa, key), getattr(sb, key)), key
+    st, it = ctx.run(sa, eps2, params, T_end, H.FP64, sync_every=16)
+    assert st == 0 and it == 0
+
+
 def test_check_finite_and_run_stops_on_nonfinite(H, ctx):
     """hermite_check_finite flags a NaN anywhere in x, v, a, j; a run of a
     system with two coincident particles and zero softening (infinite
