@@ -462,6 +462,28 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
 }
 
 constexpr int kLevelLds = 2048;   // blocks re-sorted in LDS (larger ones via L.tmp)
+constexpr int kLevelBatch = 8;    // elements per thread whose loads are issued together
+
+// Particle ids perm[p] of positions p = p0 + u kWG + tid (u < kLevelBatch)
+// and, with dt, their step sizes: every load is issued before any is used
+// (addresses clamped to the last position, so none is conditional).
+__device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int32_t p0,
+                                            int32_t (&id)[kLevelBatch], int (&b)[kLevelBatch],
+                                            bool with_steps)
+{
+#pragma unroll
+    for (int u = 0; u < kLevelBatch; ++u) {
+        const int32_t p = p0 + u * kWG + (int32_t)threadIdx.x;
+        id[u] = L.perm[p < cnt ? p : cnt - 1];
+    }
+    if (with_steps) {
+        int64_t d[kLevelBatch];
+#pragma unroll
+        for (int u = 0; u < kLevelBatch; ++u) d[u] = L.dt[id[u]];
+#pragma unroll
+        for (int u = 0; u < kLevelBatch; ++u) b[u] = log2_step(d[u]);
+    }
+}
 
 __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArgs sa)
 {
@@ -480,19 +502,27 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         s_cnt[tid] = L.cnt[tid];
     }
     __syncthreads();
+    constexpr int kStride = kWG * kLevelBatch;
 
     // 1. the previous block, ordered by the steps the corrector gave it
     if (na_prev > 0) {
         Tlast = T_prev;
         const bool lds = na_prev <= kLevelLds;
-        for (int p = tid; p < na_prev; p += kWG) {
-            const int32_t i = L.perm[p];
-            const int b = log2_step(L.dt[i]);
-            if (lds) {
-                s_id[p] = i;
-                s_lv[p] = (uint8_t)b;
+        for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(L, na_prev, p0, id, b, true);
+#pragma unroll
+            for (int u = 0; u < kLevelBatch; ++u) {
+                const int32_t p = p0 + u * kWG + tid;
+                if (p < na_prev) {
+                    if (lds) {
+                        s_id[p] = id[u];
+                        s_lv[p] = (uint8_t)b[u];
+                    }
+                    atomicAdd(&s_hist[b[u]], 1);
+                }
             }
-            atomicAdd(&s_hist[b], 1);
         }
         __syncthreads();
         if (tid < 64) {
@@ -508,21 +538,37 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             s_cur[tid] = x - hb;
         }
         __syncthreads();
-        int32_t* out = lds ? s_aux : L.tmp;
-        for (int p = tid; p < na_prev; p += kWG) {
-            int32_t i;
-            int b;
-            if (lds) {
-                i = s_id[p];
-                b = s_lv[p];
-            } else {
-                i = L.perm[p];
-                b = log2_step(L.dt[i]);
+        if (lds) {
+            for (int32_t p = tid; p < na_prev; p += kWG)
+                s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
+            __syncthreads();
+            for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
+        } else {
+            for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, na_prev, p0, id, b, true);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    if (p < na_prev) L.tmp[atomicAdd(&s_cur[b[u]], 1)] = id[u];
+                }
             }
-            out[atomicAdd(&s_cur[b], 1)] = i;
+            __syncthreads();
+            for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
+                int32_t v[kLevelBatch];
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    v[u] = L.tmp[p < na_prev ? p : na_prev - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    if (p < na_prev) L.perm[p] = v[u];
+                }
+            }
         }
-        __syncthreads();
-        for (int p = tid; p < na_prev; p += kWG) L.perm[p] = out[p];
         if (tid < 64) L.cnt[tid] = s_cnt[tid];
         if (tid == 0) L.misc[0] = Tlast;
         __syncthreads();
@@ -563,14 +609,22 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
         __syncthreads();
         const bool lds = na <= kLevelLds;
-        for (int p = tid; p < na; p += kWG) {
-            const int32_t i = L.perm[p];
-            const int c = upper_bound_i64(s_off, C + 1, (int64_t)i) - 1;
-            if (lds) {
-                s_id[p] = i;
-                s_aux[p] = c;
+        for (int32_t p0 = 0; p0 < na; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(L, na, p0, id, b, false);
+#pragma unroll
+            for (int u = 0; u < kLevelBatch; ++u) {
+                const int32_t p = p0 + u * kWG + tid;
+                if (p < na) {
+                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                    if (lds) {
+                        s_id[p] = id[u];
+                        s_aux[p] = c;
+                    }
+                    atomicAdd(&s_ch[c], 1);
+                }
             }
-            atomicAdd(&s_ch[c], 1);
         }
         __syncthreads();
         const int per = (C + kWG - 1) / kWG;
@@ -587,19 +641,29 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             run += k;
         }
         __syncthreads();
-        for (int p = tid; p < na; p += kWG) {
-            int32_t i;
-            int c;
-            if (lds) {
-                i = s_id[p];
-                c = s_aux[p];
-            } else {
-                i = L.perm[p];
-                c = upper_bound_i64(s_off, C + 1, (int64_t)i) - 1;
+        if (lds) {
+            for (int32_t p = tid; p < na; p += kWG) {
+                const int c = s_aux[p];
+                const int32_t pos = atomicAdd(&s_ch[c], 1);
+                L.idx[pos] = s_id[p];
+                sa.act_cluster[pos] = c;
             }
-            const int32_t pos = atomicAdd(&s_ch[c], 1);
-            L.idx[pos] = i;
-            sa.act_cluster[pos] = c;
+        } else {
+            for (int32_t p0 = 0; p0 < na; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, na, p0, id, b, false);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    if (p < na) {
+                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                        const int32_t pos = atomicAdd(&s_ch[c], 1);
+                        L.idx[pos] = id[u];
+                        sa.act_cluster[pos] = c;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
