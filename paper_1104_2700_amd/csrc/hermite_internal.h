@@ -197,8 +197,12 @@ struct LevelArgs {
     int32_t* perm;       // [n] particle ids by step size, smallest first
     int32_t* cnt;        // [64] particles with dt = 2^b ticks
     int32_t* cursor;     // [64] (building the order)
-    int64_t* misc;       // [0] T_last; [1] max t, [2] min t + dt, [3] inconsistent (checks)
+    int64_t* misc;       // [0] T_last; [1] max t, [2] min t + dt, [3] inconsistent (checks);
+                         // [4] a workgroup barrier of the selection timed out
     int32_t* tmp;        // [n] re-sort scratch for blocks beyond the LDS staging
+    int32_t* wg_hist;    // [kLevelGrid][64] per-workgroup step counts (large blocks)
+    int32_t* wg_chist;   // [kLevelGrid][kLdsClusters] per-workgroup cluster counts
+    uint32_t* bar;       // [2] workgroup barrier: arrivals, generation (zeroed once)
     int64_t T_end;
     int32_t* na;         // n_act: the previous step's in, this step's out
     int64_t* T;          // block time: the previous step's in, this step's out
@@ -212,9 +216,12 @@ struct LevelArgs {
 // (cursor zeroed) and sets T_last = max t and *na = 0.
 hipError_t launch_level_count(const LevelArgs& L, hipStream_t st);
 hipError_t launch_level_build(const LevelArgs& L, hipStream_t st);
-// One workgroup: re-sorts the previous block by its new steps, selects the
-// next block, groups it by cluster (C > 1; C <= kLdsClusters) and plans
-// the sweep.
+// Re-sorts the previous block by its new steps, selects the next block,
+// groups it by cluster (C > 1; C <= kLdsClusters) and plans the sweep.
+// Blocks up to a few thousand particles take one workgroup; larger ones are
+// shared by kLevelGrid workgroups that meet at barriers (all of them are
+// resident at once: the kernel runs alone on the stream and needs little).
+constexpr int kLevelGrid = 16;
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st);
 hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);
 

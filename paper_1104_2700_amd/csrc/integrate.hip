@@ -461,20 +461,23 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
     }
 }
 
-constexpr int kLevelLds = 2048;   // blocks re-sorted in LDS (larger ones via L.tmp)
+constexpr int kLevelLds = 2048;   // blocks handled by one workgroup, staged in LDS
 constexpr int kLevelBatch = 8;    // elements per thread whose loads are issued together
 
-// Particle ids perm[p] of positions p = p0 + u kWG + tid (u < kLevelBatch)
-// and, with dt, their step sizes: every load is issued before any is used
-// (addresses clamped to the last position, so none is conditional).
+// Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of the
+// order (positions below `split` from the re-sort scratch L.tmp, the rest
+// from L.perm) and, with_steps, their step sizes: every load is issued
+// before any is used (addresses clamped to the last position, so none is
+// conditional).
 __device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int32_t p0,
                                             int32_t (&id)[kLevelBatch], int (&b)[kLevelBatch],
-                                            bool with_steps)
+                                            bool with_steps, int32_t split = 0)
 {
 #pragma unroll
     for (int u = 0; u < kLevelBatch; ++u) {
         const int32_t p = p0 + u * kWG + (int32_t)threadIdx.x;
-        id[u] = L.perm[p < cnt ? p : cnt - 1];
+        const int32_t pc = p < cnt ? p : cnt - 1;
+        id[u] = (pc < split ? L.tmp : L.perm)[pc];
     }
     if (with_steps) {
         int64_t d[kLevelBatch];
@@ -485,6 +488,37 @@ __device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int
     }
 }
 
+// Barrier of all workgroups of the selection (every one calls it at the
+// same points).  The wait is bounded: past the limit it records the
+// timeout in misc[4] and goes on, so the kernel always ends.
+__device__ void level_barrier(const LevelArgs& L)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* count = L.bar;
+        uint32_t* gen = L.bar + 1;
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived =
+            __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int64_t spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins > (int64_t(1) << 22)) {
+                    __hip_atomic_store(&L.misc[4], (int64_t)1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArgs sa)
 {
     __shared__ int32_t s_hist[64], s_cur[64], s_cnt[64];
@@ -493,10 +527,17 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     __shared__ uint8_t s_lv[kLevelLds];
     __shared__ int32_t s_scan[kWG / 64];
     __shared__ int32_t s_na;
+    __shared__ int64_t s_off[kLdsClusters + 1];
+    __shared__ int32_t s_ch[kLdsClusters];
     const int tid = threadIdx.x;
+    const int G = gridDim.x, g = blockIdx.x;
+    const int C = sa.n_clusters;
     const int32_t na_prev = *L.na;
     const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
+    const bool r_big = na_prev > kLevelLds;
+    // one system after a small block: workgroup 0 does everything
+    if (g > 0 && !r_big && C == 1) return;
     if (tid < 64) {
         s_hist[tid] = 0;
         s_cnt[tid] = L.cnt[tid];
@@ -505,45 +546,13 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     constexpr int kStride = kWG * kLevelBatch;
 
     // 1. the previous block, ordered by the steps the corrector gave it
+    // (every particle whose step divides T_prev was in that block)
     if (na_prev > 0) {
         Tlast = T_prev;
-        const bool lds = na_prev <= kLevelLds;
-        for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
-            int32_t id[kLevelBatch];
-            int b[kLevelBatch];
-            level_batch(L, na_prev, p0, id, b, true);
-#pragma unroll
-            for (int u = 0; u < kLevelBatch; ++u) {
-                const int32_t p = p0 + u * kWG + tid;
-                if (p < na_prev) {
-                    if (lds) {
-                        s_id[p] = id[u];
-                        s_lv[p] = (uint8_t)b[u];
-                    }
-                    atomicAdd(&s_hist[b[u]], 1);
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < 64) {
-            // every particle whose step divides T_prev was in that block
-            const int z = __builtin_ctzll((unsigned long long)T_prev);
-            const int32_t hb = s_hist[tid];
-            s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + hb;
-            int32_t x = hb;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int32_t u = __shfl_up(x, o);
-                if (tid >= o) x += u;
-            }
-            s_cur[tid] = x - hb;
-        }
-        __syncthreads();
-        if (lds) {
-            for (int32_t p = tid; p < na_prev; p += kWG)
-                s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
-            __syncthreads();
-            for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
-        } else {
+        const int z = __builtin_ctzll((unsigned long long)T_prev);
+        if (!r_big) {
+            // its step counts (every workgroup, to know the next block's
+            // size); workgroup 0 re-sorts it in LDS
             for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
                 int32_t id[kLevelBatch];
                 int b[kLevelBatch];
@@ -551,30 +560,96 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
 #pragma unroll
                 for (int u = 0; u < kLevelBatch; ++u) {
                     const int32_t p = p0 + u * kWG + tid;
-                    if (p < na_prev) L.tmp[atomicAdd(&s_cur[b[u]], 1)] = id[u];
+                    if (p < na_prev) {
+                        s_id[p] = id[u];
+                        s_lv[p] = (uint8_t)b[u];
+                        atomicAdd(&s_hist[b[u]], 1);
+                    }
                 }
             }
             __syncthreads();
-            for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
+            if (tid < 64) {
+                const int32_t hb = s_hist[tid];
+                s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + hb;
+                int32_t x = hb;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int32_t u = __shfl_up(x, o);
+                    if (tid >= o) x += u;
+                }
+                s_cur[tid] = x - hb;
+            }
+            __syncthreads();
+            if (g == 0) {
+                for (int32_t p = tid; p < na_prev; p += kWG)
+                    s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
+                __syncthreads();
+                for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
+            }
+        } else {
+            // shared by all workgroups: per-slice counts, the order of
+            // (step size, workgroup), scatter, copy back
+            const int32_t per = (na_prev + G - 1) / G;
+            const int32_t q0 = g * per < na_prev ? g * per : na_prev;
+            const int32_t q1 = q0 + per < na_prev ? q0 + per : na_prev;
+            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, q1, p0, id, b, true);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u)
+                    if (p0 + u * kWG + tid < q1) atomicAdd(&s_hist[b[u]], 1);
+            }
+            __syncthreads();
+            if (tid < 64) L.wg_hist[g * 64 + tid] = s_hist[tid];
+            level_barrier(L);
+            if (tid < 64) {
+                int32_t total = 0, before = 0;
+                for (int w = 0; w < G; ++w) {
+                    const int32_t v = L.wg_hist[w * 64 + tid];
+                    total += v;
+                    before += w < g ? v : 0;
+                }
+                s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + total;
+                int32_t x = total;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int32_t u = __shfl_up(x, o);
+                    if (tid >= o) x += u;
+                }
+                s_cur[tid] = x - total + before;
+            }
+            __syncthreads();
+            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, q1, p0, id, b, true);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u)
+                    if (p0 + u * kWG + tid < q1) L.tmp[atomicAdd(&s_cur[b[u]], 1)] = id[u];
+            }
+            level_barrier(L);
+            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
                 int32_t v[kLevelBatch];
 #pragma unroll
                 for (int u = 0; u < kLevelBatch; ++u) {
                     const int32_t p = p0 + u * kWG + tid;
-                    v[u] = L.tmp[p < na_prev ? p : na_prev - 1];
+                    v[u] = L.tmp[p < q1 ? p : q1 - 1];
                 }
 #pragma unroll
                 for (int u = 0; u < kLevelBatch; ++u) {
                     const int32_t p = p0 + u * kWG + tid;
-                    if (p < na_prev) L.perm[p] = v[u];
+                    if (p < q1) L.perm[p] = v[u];
                 }
             }
         }
-        if (tid < 64) L.cnt[tid] = s_cnt[tid];
-        if (tid == 0) L.misc[0] = Tlast;
+        if (g == 0) {
+            if (tid < 64) L.cnt[tid] = s_cnt[tid];
+            if (tid == 0) L.misc[0] = Tlast;
+        }
         __syncthreads();
     }
 
-    // 2. next block time and active count (wave 0, one lane per step size)
+    // 2. next block time and active count (wave 0, one lane per step size;
+    // every workgroup gets the same answer)
     if (tid < 64) {
         const int32_t c = s_cnt[tid];
         const unsigned long long occ = __ballot(c > 0);
@@ -583,91 +658,119 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         if (occ != 0ull) {
             const int bmin = __builtin_ctzll(occ);
             Tn = ((Tlast >> bmin) + 1) << bmin;
-            const int z = __builtin_ctzll((unsigned long long)Tn);
-            int32_t v = tid <= z ? c : 0;
+            const int zn = __builtin_ctzll((unsigned long long)Tn);
+            int32_t v = tid <= zn ? c : 0;
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
             na = v;
         }
         if (Tn > L.T_end) na = 0;
         if (tid == 0) {
             s_na = na;
-            *L.T = Tn;
-            *L.na = na;
-            count_step(L.counters, Tn, na);
+            if (g == 0) {
+                *L.T = Tn;
+                *L.na = na;
+                count_step(L.counters, Tn, na);
+            }
         }
     }
     __syncthreads();
     const int32_t na = s_na;
+    if (C == 1 || na == 0) {
+        if (g == 0) plan_body(sa, na);
+        return;
+    }
 
-    // 3. with clusters: the block grouped by cluster (counting sort), with
-    // every cluster's first position and every position's cluster
-    const int C = sa.n_clusters;
-    if (C > 1 && na > 0) {
-        __shared__ int64_t s_off[kLdsClusters + 1];
-        __shared__ int32_t s_ch[kLdsClusters];
-        for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
-        for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
-        __syncthreads();
-        const bool lds = na <= kLevelLds;
-        for (int32_t p0 = 0; p0 < na; p0 += kStride) {
-            int32_t id[kLevelBatch];
-            int b[kLevelBatch];
-            level_batch(L, na, p0, id, b, false);
+    // 3. the block grouped by cluster (counting sort), with every cluster's
+    // first position and every position's cluster
+    // After a shared re-sort the block's first na_prev positions are read
+    // from the scratch (complete since the last barrier; the copy back to
+    // perm may still be under way).  A re-sort by workgroup 0 alone must be
+    // complete before a shared grouping reads it.
+    const bool c_big = na > kLevelLds;
+    const int32_t split = r_big ? na_prev : 0;
+    if (c_big && !r_big) level_barrier(L);
+    if (!c_big && g > 0) return;
+    for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
+    for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
+    __syncthreads();
+    const int32_t per = c_big ? (na + G - 1) / G : na;
+    const int32_t q0 = g * per < na ? g * per : na;
+    const int32_t q1 = q0 + per < na ? q0 + per : na;
+    for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+        int32_t id[kLevelBatch];
+        int b[kLevelBatch];
+        level_batch(L, q1, p0, id, b, false, split);
 #pragma unroll
-            for (int u = 0; u < kLevelBatch; ++u) {
-                const int32_t p = p0 + u * kWG + tid;
-                if (p < na) {
-                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                    if (lds) {
-                        s_id[p] = id[u];
-                        s_aux[p] = c;
-                    }
-                    atomicAdd(&s_ch[c], 1);
+        for (int u = 0; u < kLevelBatch; ++u) {
+            const int32_t p = p0 + u * kWG + tid;
+            if (p < q1) {
+                const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                if (!c_big) {
+                    s_id[p] = id[u];
+                    s_aux[p] = c;
                 }
+                atomicAdd(&s_ch[c], 1);
             }
         }
-        __syncthreads();
-        const int per = (C + kWG - 1) / kWG;
-        const int c0 = tid * per < C ? tid * per : C;
-        const int c1 = c0 + per < C ? c0 + per : C;
-        int32_t loc = 0;
-        for (int c = c0; c < c1; ++c) loc += s_ch[c];
-        int32_t tot;
-        int32_t run = block_exscan_i32(loc, s_scan, &tot);
+    }
+    __syncthreads();
+    // thread t owns clusters [c0, c1): their totals, this workgroup's offset
+    // within each, and the clusters' first positions
+    const int cper = (C + kWG - 1) / kWG;
+    const int c0 = tid * cper < C ? tid * cper : C;
+    const int c1 = c0 + cper < C ? c0 + cper : C;
+    if (c_big) {
+        for (int c = c0; c < c1; ++c) L.wg_chist[g * kLdsClusters + c] = s_ch[c];
+        level_barrier(L);
         for (int c = c0; c < c1; ++c) {
-            const int32_t k = s_ch[c];
-            s_ch[c] = run;
-            sa.act_start[c] = run;
-            run += k;
-        }
-        __syncthreads();
-        if (lds) {
-            for (int32_t p = tid; p < na; p += kWG) {
-                const int c = s_aux[p];
-                const int32_t pos = atomicAdd(&s_ch[c], 1);
-                L.idx[pos] = s_id[p];
-                sa.act_cluster[pos] = c;
+            int32_t total = 0, before = 0;
+            for (int w = 0; w < G; ++w) {
+                const int32_t v = L.wg_chist[w * kLdsClusters + c];
+                total += v;
+                before += w < g ? v : 0;
             }
-        } else {
-            for (int32_t p0 = 0; p0 < na; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, na, p0, id, b, false);
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    if (p < na) {
-                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                        const int32_t pos = atomicAdd(&s_ch[c], 1);
-                        L.idx[pos] = id[u];
-                        sa.act_cluster[pos] = c;
-                    }
-                }
-            }
+            s_ch[c] = total;
+            s_aux[c] = before;
         }
         __syncthreads();
     }
-    plan_body(sa, na);
+    int32_t loc = 0;
+    for (int c = c0; c < c1; ++c) loc += s_ch[c];
+    int32_t tot;
+    int32_t run = block_exscan_i32(loc, s_scan, &tot);
+    for (int c = c0; c < c1; ++c) {
+        const int32_t k = s_ch[c];
+        s_ch[c] = run + (c_big ? s_aux[c] : 0);
+        if (g == 0) sa.act_start[c] = run;
+        run += k;
+    }
+    __syncthreads();
+    if (!c_big) {
+        for (int32_t p = tid; p < na; p += kWG) {
+            const int c = s_aux[p];
+            const int32_t pos = atomicAdd(&s_ch[c], 1);
+            L.idx[pos] = s_id[p];
+            sa.act_cluster[pos] = c;
+        }
+    } else {
+        for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(L, q1, p0, id, b, false, split);
+#pragma unroll
+            for (int u = 0; u < kLevelBatch; ++u) {
+                const int32_t p = p0 + u * kWG + tid;
+                if (p < q1) {
+                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                    const int32_t pos = atomicAdd(&s_ch[c], 1);
+                    L.idx[pos] = id[u];
+                    sa.act_cluster[pos] = c;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (g == 0) plan_body(sa, na);
 }
 
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
@@ -958,7 +1061,7 @@ hipError_t launch_level_build(const LevelArgs& L, hipStream_t st)
 
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st)
 {
-    hipLaunchKernelGGL(level_select_kernel, dim3(1), dim3(kWG), 0, st, L, sa);
+    hipLaunchKernelGGL(level_select_kernel, dim3(kLevelGrid), dim3(kWG), 0, st, L, sa);
     return hipGetLastError();
 }
 
