@@ -202,7 +202,10 @@ struct LevelArgs {
     int32_t* tmp;        // [n] re-sort scratch for blocks beyond the LDS staging
     int32_t* wg_hist;    // [kLevelGrid][64] per-workgroup step counts (large blocks)
     int32_t* wg_chist;   // [kLevelGrid][kLdsClusters] per-workgroup cluster counts
-    uint32_t* bar;       // [2] workgroup barrier: arrivals, generation (zeroed once)
+    uint32_t* bar;       // [4] workgroup barrier: arrivals, generation; [2], [3]
+                         // n_act posted by workgroup 0 and its readers (all
+                         // zeroed once, left zero)
+    uint32_t* bits;      // [(n + 31) / 32] active-particle bitmap (zeroed once, left zero)
     int64_t T_end;
     int32_t* na;         // n_act: the previous step's in, this step's out
     int64_t* T;          // block time: the previous step's in, this step's out

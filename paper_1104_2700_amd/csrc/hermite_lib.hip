@@ -75,7 +75,7 @@ struct hermite_ctx {
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
-    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_wg, lvl_wgc, lvl_bar;
+    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_wg, lvl_wgc, lvl_bar, lvl_bits;
     std::vector<GraphEntry> graphs;
     // grid of the fused select + sweep for the last shape it was sized for
     struct {
@@ -279,6 +279,7 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_dt_pa
     L.wg_hist = (int32_t*)c->lvl_wg.p;
     L.wg_chist = (int32_t*)c->lvl_wgc.p;
     L.bar = (uint32_t*)c->lvl_bar.p;
+    L.bits = (uint32_t*)c->lvl_bits.p;
     L.T_end = T_end;
     L.na = (int32_t*)c->step_na.p;
     L.T = (int64_t*)c->step_T.p;
@@ -301,13 +302,15 @@ int level_init(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* 
     CHECK(ensure(c, c->lvl_misc, sizeof(int64_t) * 8));
     CHECK(ensure(c, c->lvl_wg, sizeof(int32_t) * kLevelGrid * 64));
     CHECK(ensure(c, c->lvl_wgc, sizeof(int32_t) * kLevelGrid * kLdsClusters));
-    CHECK(ensure(c, c->lvl_bar, sizeof(uint32_t) * 2));
+    CHECK(ensure(c, c->lvl_bar, sizeof(uint32_t) * 4));
+    CHECK(ensure(c, c->lvl_bits, sizeof(uint32_t) * ((s->n + 31) / 32)));
     const LevelArgs L = level_args(c, s, p, 0);
     const int64_t init[8] = {0, INT64_MIN, INT64_MAX, 0, 0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(L.misc, init, sizeof init, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * 64, st));
     HIP_OK(hipMemsetAsync(L.cursor, 0, sizeof(int32_t) * 64, st));
-    HIP_OK(hipMemsetAsync(L.bar, 0, sizeof(uint32_t) * 2, st));
+    HIP_OK(hipMemsetAsync(L.bar, 0, sizeof(uint32_t) * 4, st));
+    HIP_OK(hipMemsetAsync(L.bits, 0, sizeof(uint32_t) * ((s->n + 31) / 32), st));
     HIP_OK(launch_level_count(L, st));
     int64_t h[4];
     HIP_OK(hipMemcpyAsync(h, L.misc, sizeof h, hipMemcpyDeviceToHost, st));

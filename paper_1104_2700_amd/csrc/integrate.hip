@@ -536,8 +536,6 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
     const bool r_big = na_prev > kLevelLds;
-    // one system after a small block: workgroup 0 does everything
-    if (g > 0 && !r_big && C == 1) return;
     if (tid < 64) {
         s_hist[tid] = 0;
         s_cnt[tid] = L.cnt[tid];
@@ -546,13 +544,12 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     constexpr int kStride = kWG * kLevelBatch;
 
     // 1. the previous block, ordered by the steps the corrector gave it
-    // (every particle whose step divides T_prev was in that block)
-    if (na_prev > 0) {
+    // (every particle whose step divides T_prev was in that block): by
+    // workgroup 0 alone when it is small, by all workgroups when large
+    if (na_prev > 0 && (r_big || g == 0)) {
         Tlast = T_prev;
         const int z = __builtin_ctzll((unsigned long long)T_prev);
         if (!r_big) {
-            // its step counts (every workgroup, to know the next block's
-            // size); workgroup 0 re-sorts it in LDS
             for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
                 int32_t id[kLevelBatch];
                 int b[kLevelBatch];
@@ -579,12 +576,10 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
                 s_cur[tid] = x - hb;
             }
             __syncthreads();
-            if (g == 0) {
-                for (int32_t p = tid; p < na_prev; p += kWG)
-                    s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
-                __syncthreads();
-                for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
-            }
+            for (int32_t p = tid; p < na_prev; p += kWG)
+                s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
+            __syncthreads();
+            for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
         } else {
             // shared by all workgroups: per-slice counts, the order of
             // (step size, workgroup), scatter, copy back
@@ -648,128 +643,191 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         __syncthreads();
     }
 
-    // 2. next block time and active count (wave 0, one lane per step size;
-    // every workgroup gets the same answer)
-    if (tid < 64) {
-        const int32_t c = s_cnt[tid];
-        const unsigned long long occ = __ballot(c > 0);
-        int64_t Tn = INT64_MAX;
-        int32_t na = 0;
-        if (occ != 0ull) {
-            const int bmin = __builtin_ctzll(occ);
-            Tn = ((Tlast >> bmin) + 1) << bmin;
-            const int zn = __builtin_ctzll((unsigned long long)Tn);
-            int32_t v = tid <= zn ? c : 0;
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            na = v;
-        }
-        if (Tn > L.T_end) na = 0;
-        if (tid == 0) {
-            s_na = na;
-            if (g == 0) {
-                *L.T = Tn;
-                *L.na = na;
-                count_step(L.counters, Tn, na);
+    // 2. next block time and active count (wave 0, one lane per step
+    // size).  After a small block only workgroup 0 knows them: it posts
+    // n_act + 1 in bar[3]; the others take it from there, and the last of
+    // them to do so clears bar[3] and the count bar[2] for the next call.
+    if (r_big || g == 0) {
+        if (tid < 64) {
+            const int32_t cz = s_cnt[tid];
+            const unsigned long long occ = __ballot(cz > 0);
+            int64_t Tn = INT64_MAX;
+            int32_t na = 0;
+            if (occ != 0ull) {
+                const int bmin = __builtin_ctzll(occ);
+                Tn = ((Tlast >> bmin) + 1) << bmin;
+                const int zn = __builtin_ctzll((unsigned long long)Tn);
+                int32_t v = tid <= zn ? cz : 0;
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                na = v;
             }
+            if (Tn > L.T_end) na = 0;
+            if (tid == 0) {
+                s_na = na;
+                if (g == 0) {
+                    *L.T = Tn;
+                    *L.na = na;
+                    count_step(L.counters, Tn, na);
+                    if (!r_big)
+                        __hip_atomic_store(&L.bar[3], (uint32_t)na + 1u, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    } else if (tid == 0) {
+        int64_t spins = 0;
+        uint32_t f;
+        while ((f = __hip_atomic_load(&L.bar[3], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) ==
+               0u) {
+            if (++spins > (int64_t(1) << 22)) {
+                __hip_atomic_store(&L.misc[4], (int64_t)1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                f = 1u;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_na = (int32_t)(f - 1u);
+        if (__hip_atomic_fetch_add(&L.bar[2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+            gridDim.x - 2) {
+            __hip_atomic_store(&L.bar[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&L.bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
     const int32_t na = s_na;
-    if (C == 1 || na == 0) {
+    const bool big = na > kLevelLds;
+    if (na == 0 || (!big && g > 0)) {
         if (g == 0) plan_body(sa, na);
         return;
     }
-
-    // 3. the block grouped by cluster (counting sort), with every cluster's
-    // first position and every position's cluster
     // After a shared re-sort the block's first na_prev positions are read
     // from the scratch (complete since the last barrier; the copy back to
-    // perm may still be under way).  A re-sort by workgroup 0 alone must be
-    // complete before a shared grouping reads it.
-    const bool c_big = na > kLevelLds;
+    // perm may still be under way).
     const int32_t split = r_big ? na_prev : 0;
-    if (c_big && !r_big) level_barrier(L);
-    if (!c_big && g > 0) return;
-    for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
-    for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
-    __syncthreads();
-    const int32_t per = c_big ? (na + G - 1) / G : na;
-    const int32_t q0 = g * per < na ? g * per : na;
-    const int32_t q1 = q0 + per < na ? q0 + per : na;
-    for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-        int32_t id[kLevelBatch];
-        int b[kLevelBatch];
-        level_batch(L, q1, p0, id, b, false, split);
-#pragma unroll
-        for (int u = 0; u < kLevelBatch; ++u) {
-            const int32_t p = p0 + u * kWG + tid;
-            if (p < q1) {
-                const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                if (!c_big) {
-                    s_id[p] = id[u];
-                    s_aux[p] = c;
-                }
-                atomicAdd(&s_ch[c], 1);
-            }
-        }
-    }
-    __syncthreads();
-    // thread t owns clusters [c0, c1): their totals, this workgroup's offset
-    // within each, and the clusters' first positions
-    const int cper = (C + kWG - 1) / kWG;
-    const int c0 = tid * cper < C ? tid * cper : C;
-    const int c1 = c0 + cper < C ? c0 + cper : C;
-    if (c_big) {
-        for (int c = c0; c < c1; ++c) L.wg_chist[g * kLdsClusters + c] = s_ch[c];
-        level_barrier(L);
-        for (int c = c0; c < c1; ++c) {
-            int32_t total = 0, before = 0;
-            for (int w = 0; w < G; ++w) {
-                const int32_t v = L.wg_chist[w * kLdsClusters + c];
-                total += v;
-                before += w < g ? v : 0;
-            }
-            s_ch[c] = total;
-            s_aux[c] = before;
-        }
+    if (C > 1) {
+        for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
+        for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
         __syncthreads();
     }
-    int32_t loc = 0;
-    for (int c = c0; c < c1; ++c) loc += s_ch[c];
-    int32_t tot;
-    int32_t run = block_exscan_i32(loc, s_scan, &tot);
-    for (int c = c0; c < c1; ++c) {
-        const int32_t k = s_ch[c];
-        s_ch[c] = run + (c_big ? s_aux[c] : 0);
-        if (g == 0) sa.act_start[c] = run;
-        run += k;
-    }
-    __syncthreads();
-    if (!c_big) {
-        for (int32_t p = tid; p < na; p += kWG) {
-            const int c = s_aux[p];
-            const int32_t pos = atomicAdd(&s_ch[c], 1);
-            L.idx[pos] = s_id[p];
-            sa.act_cluster[pos] = c;
+
+    if (!big) {
+        // 3. a small block (workgroup 0): with clusters, grouped by cluster
+        // (counting sort) with every cluster's first position and every
+        // position's cluster; one system uses the prefix of the order as is
+        if (C > 1) {
+            for (int32_t p0 = 0; p0 < na; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, na, p0, id, b, false, split);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    if (p < na) {
+                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                        s_id[p] = id[u];
+                        s_aux[p] = c;
+                        atomicAdd(&s_ch[c], 1);
+                    }
+                }
+            }
+            __syncthreads();
+            const int cper = (C + kWG - 1) / kWG;
+            const int c0 = tid * cper < C ? tid * cper : C;
+            const int c1 = c0 + cper < C ? c0 + cper : C;
+            int32_t loc = 0;
+            for (int c = c0; c < c1; ++c) loc += s_ch[c];
+            int32_t tot;
+            int32_t run = block_exscan_i32(loc, s_scan, &tot);
+            for (int c = c0; c < c1; ++c) {
+                const int32_t k = s_ch[c];
+                s_ch[c] = run;
+                sa.act_start[c] = run;
+                run += k;
+            }
+            __syncthreads();
+            for (int32_t p = tid; p < na; p += kWG) {
+                const int c = s_aux[p];
+                const int32_t pos = atomicAdd(&s_ch[c], 1);
+                L.idx[pos] = s_id[p];
+                sa.act_cluster[pos] = c;
+            }
+            __syncthreads();
         }
-    } else {
+        plan_body(sa, na);
+        return;
+    }
+
+    // 3. a large block (all workgroups): listed in ascending particle order
+    // through a bitmap of the active particles, so that every wave's
+    // particles lie close together (fewer j-tiles need the self-pair
+    // mask).  Ascending order is also grouped by cluster.  One system
+    // rewrites the prefix of the order (its order within the prefix is
+    // free: the next re-sort reorders it).
+    if (!r_big) level_barrier(L);   // workgroup 0's re-sort is complete
+    {
+        const int32_t per = (na + G - 1) / G;
+        const int32_t q0 = g * per < na ? g * per : na;
+        const int32_t q1 = q0 + per < na ? q0 + per : na;
         for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
             int32_t id[kLevelBatch];
             int b[kLevelBatch];
             level_batch(L, q1, p0, id, b, false, split);
 #pragma unroll
-            for (int u = 0; u < kLevelBatch; ++u) {
-                const int32_t p = p0 + u * kWG + tid;
-                if (p < q1) {
-                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                    const int32_t pos = atomicAdd(&s_ch[c], 1);
-                    L.idx[pos] = id[u];
-                    sa.act_cluster[pos] = c;
-                }
-            }
+            for (int u = 0; u < kLevelBatch; ++u)
+                if (p0 + u * kWG + tid < q1)
+                    atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
         }
     }
-    __syncthreads();
+    level_barrier(L);
+    // workgroup g owns words [w0, w1) of the bitmap, thread t a contiguous
+    // run [wa, wb) of them
+    const int64_t nw = (L.n + 31) >> 5;
+    const int64_t wper = (nw + G - 1) / G;
+    const int64_t w0 = (int64_t)g * wper < nw ? (int64_t)g * wper : nw;
+    const int64_t w1 = w0 + wper < nw ? w0 + wper : nw;
+    const int64_t tper = (w1 - w0 + kWG - 1) / kWG;
+    const int64_t wa = w0 + tid * tper < w1 ? w0 + tid * tper : w1;
+    const int64_t wb = wa + tper < w1 ? wa + tper : w1;
+    int32_t cnt = 0;
+    for (int64_t w = wa; w < wb; ++w) cnt += __popc(L.bits[w]);
+    int32_t wg_total;
+    const int32_t pre = block_exscan_i32(cnt, s_scan, &wg_total);
+    if (tid == 0) L.wg_hist[g * 64] = wg_total;
+    level_barrier(L);
+    int32_t pos = pre;
+    for (int w = 0; w < g; ++w) pos += L.wg_hist[w * 64];
+    int32_t* out = C == 1 ? L.perm : L.idx;
+    int cn = 0, cur = 0;
+    if (C > 1) {
+        cn = lower_bound_i64(s_off, C, wa << 5);            // first cluster start >= 32 wa
+        cur = upper_bound_i64(s_off, C + 1, wa << 5) - 1;   // cluster of index 32 wa
+    }
+    for (int64_t w = wa; w < wb; ++w) {
+        uint32_t word = L.bits[w];
+        L.bits[w] = 0u;
+        if (C > 1) {
+            while (cn < C && s_off[cn] < ((w + 1) << 5)) {
+                const int sh = (int)(s_off[cn] - (w << 5));
+                sa.act_start[cn] = pos + __popc(word & ((1u << sh) - 1u));
+                ++cn;
+            }
+        }
+        while (word) {
+            const int32_t i = (int32_t)((w << 5) + __builtin_ctz(word));
+            word &= word - 1u;
+            if (C > 1) {
+                while (cur + 1 < C && s_off[cur + 1] <= i) ++cur;
+                sa.act_cluster[pos] = cur;
+            }
+            out[pos++] = i;
+        }
+    }
+    if (C == 1) {
+        if (g == 0) plan_body(sa, na);
+        return;
+    }
+    level_barrier(L);   // every cluster's first position is written
     if (g == 0) plan_body(sa, na);
 }
 
