@@ -240,10 +240,28 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
  * launched (max_steps <= 0: no limit; the call can then be repeated to
  * continue).  The host reads the device block time once every sync_every
  * steps, and then also checks the state as hermite_check_finite does:
- * a non-finite state ends the call with HERMITE_ENONFINITE.  With use_graph != 0, runs of 8 consecutive steps are captured as
- * one graph (steps past T_end are no-ops), which removes the gap between
- * graph launches that dominates small systems.  steps_out / interactions_out (host, may be NULL) receive the
- * block-step count and the number of pair interactions (sum over steps of
+ * a non-finite state ends the call with HERMITE_ENONFINITE.  With
+ * use_graph != 0, runs of 8 consecutive steps are captured as one graph
+ * (steps past T_end are no-ops), which removes the gap between graph
+ * launches that dominates small systems.
+ *
+ * Block selection in a run (Section 2's block scheme): at the start of the
+ * call the particles are ordered by step size (one pass over t and dt,
+ * synchronising `stream`).  When every dt_i is a power of two no finer
+ * than 2^(tick_bits - k_max), every t_i a multiple of dt_i and no particle
+ * is due before the latest t, the next block time is the first multiple of
+ * the smallest occupied step after the last block time and the active
+ * block is a prefix of that order, so each step selects in O(n_act) (one
+ * kernel) instead of scanning t and dt; otherwise, and for one system of
+ * n <= 2048 (selected inside the sweep) or more than 2048 clusters, the
+ * run selects as hermite_step does.  Both give the same state bit for bit.
+ * Large blocks are shared by 16 workgroups that wait for each other with
+ * bounded waits; should a wait run out (the workgroups could not run at
+ * the same time, e.g. a device filled by other work), the call returns
+ * HERMITE_EHIP with a message and the state is not to be trusted.
+ *
+ * steps_out / interactions_out (host, may be NULL) receive the block-step
+ * count and the number of pair interactions (sum over steps of
  * sum_i n_c(i)) of this call; done_out (host, may be NULL) is set to 1 when
  * every particle has reached T_end. */
 int hermite_run(hermite_ctx* ctx, const hermite_state* s,

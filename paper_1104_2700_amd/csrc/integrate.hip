@@ -463,6 +463,7 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
 
 constexpr int kLevelLds = 2048;   // blocks handled by one workgroup, staged in LDS
 constexpr int kLevelBatch = 8;    // elements per thread whose loads are issued together
+constexpr int kLevelOrder = 8192; // one system: blocks workgroup 0 lists in particle order
 
 // Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of the
 // order (positions below `split` from the re-sort scratch L.tmp, the rest
@@ -536,6 +537,8 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
     const bool r_big = na_prev > kLevelLds;
+    // one system after a small block: workgroup 0 does everything
+    if (g > 0 && C == 1 && !r_big) return;
     if (tid < 64) {
         s_hist[tid] = 0;
         s_cnt[tid] = L.cnt[tid];
@@ -644,9 +647,10 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     }
 
     // 2. next block time and active count (wave 0, one lane per step
-    // size).  After a small block only workgroup 0 knows them: it posts
-    // n_act + 1 in bar[3]; the others take it from there, and the last of
-    // them to do so clears bar[3] and the count bar[2] for the next call.
+    // size).  After a small block only workgroup 0 knows them; with
+    // clusters it posts n_act + 1 in bar[3], the others take it from there,
+    // and the last of them to do so clears bar[3] and the count bar[2] for
+    // the next call.
     if (r_big || g == 0) {
         if (tid < 64) {
             const int32_t cz = s_cnt[tid];
@@ -668,7 +672,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
                     *L.T = Tn;
                     *L.na = na;
                     count_step(L.counters, Tn, na);
-                    if (!r_big)
+                    if (!r_big && C > 1)
                         __hip_atomic_store(&L.bar[3], (uint32_t)na + 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -696,9 +700,25 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     }
     __syncthreads();
     const int32_t na = s_na;
-    const bool big = na > kLevelLds;
-    if (na == 0 || (!big && g > 0)) {
+    // Workgroups that list the block in ascending particle order (0: the
+    // block is used as the order's prefix, or, with clusters, grouped by a
+    // counting sort in LDS).  Ascending order pays on large blocks: a
+    // wave's particles then lie close together and fewer j-tiles need the
+    // self-pair mask.  One system lists a large block with every workgroup
+    // after a large block, with workgroup 0 alone (only above kLevelOrder)
+    // after a small one, when the others have already left.
+    int parts = 0;
+    if (C == 1)
+        parts = (r_big && na > kLevelLds) ? G : ((!r_big && na > kLevelOrder) ? 1 : 0);
+    else
+        parts = na > kLevelLds ? G : 0;
+    if (na == 0) {
         if (g == 0) plan_body(sa, na);
+        return;
+    }
+    if (g > 0 && parts < G) return;   // workgroup 0 alone from here
+    if (C == 1 && parts == 0) {
+        plan_body(sa, na);
         return;
     }
     // After a shared re-sort the block's first na_prev positions are read
@@ -711,63 +731,61 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         __syncthreads();
     }
 
-    if (!big) {
-        // 3. a small block (workgroup 0): with clusters, grouped by cluster
+    if (parts == 0) {
+        // 3. a small block with clusters (workgroup 0): grouped by cluster
         // (counting sort) with every cluster's first position and every
-        // position's cluster; one system uses the prefix of the order as is
-        if (C > 1) {
-            for (int32_t p0 = 0; p0 < na; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, na, p0, id, b, false, split);
+        // position's cluster
+        for (int32_t p0 = 0; p0 < na; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(L, na, p0, id, b, false, split);
 #pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    if (p < na) {
-                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                        s_id[p] = id[u];
-                        s_aux[p] = c;
-                        atomicAdd(&s_ch[c], 1);
-                    }
+            for (int u = 0; u < kLevelBatch; ++u) {
+                const int32_t p = p0 + u * kWG + tid;
+                if (p < na) {
+                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                    s_id[p] = id[u];
+                    s_aux[p] = c;
+                    atomicAdd(&s_ch[c], 1);
                 }
             }
-            __syncthreads();
-            const int cper = (C + kWG - 1) / kWG;
-            const int c0 = tid * cper < C ? tid * cper : C;
-            const int c1 = c0 + cper < C ? c0 + cper : C;
-            int32_t loc = 0;
-            for (int c = c0; c < c1; ++c) loc += s_ch[c];
-            int32_t tot;
-            int32_t run = block_exscan_i32(loc, s_scan, &tot);
-            for (int c = c0; c < c1; ++c) {
-                const int32_t k = s_ch[c];
-                s_ch[c] = run;
-                sa.act_start[c] = run;
-                run += k;
-            }
-            __syncthreads();
-            for (int32_t p = tid; p < na; p += kWG) {
-                const int c = s_aux[p];
-                const int32_t pos = atomicAdd(&s_ch[c], 1);
-                L.idx[pos] = s_id[p];
-                sa.act_cluster[pos] = c;
-            }
-            __syncthreads();
         }
+        __syncthreads();
+        const int cper = (C + kWG - 1) / kWG;
+        const int c0 = tid * cper < C ? tid * cper : C;
+        const int c1 = c0 + cper < C ? c0 + cper : C;
+        int32_t loc = 0;
+        for (int c = c0; c < c1; ++c) loc += s_ch[c];
+        int32_t tot;
+        int32_t run = block_exscan_i32(loc, s_scan, &tot);
+        for (int c = c0; c < c1; ++c) {
+            const int32_t k = s_ch[c];
+            s_ch[c] = run;
+            sa.act_start[c] = run;
+            run += k;
+        }
+        __syncthreads();
+        for (int32_t p = tid; p < na; p += kWG) {
+            const int c = s_aux[p];
+            const int32_t pos = atomicAdd(&s_ch[c], 1);
+            L.idx[pos] = s_id[p];
+            sa.act_cluster[pos] = c;
+        }
+        __syncthreads();
         plan_body(sa, na);
         return;
     }
 
-    // 3. a large block (all workgroups): listed in ascending particle order
-    // through a bitmap of the active particles, so that every wave's
-    // particles lie close together (fewer j-tiles need the self-pair
-    // mask).  Ascending order is also grouped by cluster.  One system
-    // rewrites the prefix of the order (its order within the prefix is
-    // free: the next re-sort reorders it).
-    if (!r_big) level_barrier(L);   // workgroup 0's re-sort is complete
+    // 3. a large block in ascending particle order, through a bitmap of the
+    // active particles (ascending order is also grouped by cluster).  One
+    // system rewrites the prefix of the order (its order within the prefix
+    // is free: the next re-sort reorders it).
+    const bool shared = parts > 1;
+    const int gp = shared ? g : 0;
+    if (shared && !r_big) level_barrier(L);   // workgroup 0's re-sort is complete
     {
-        const int32_t per = (na + G - 1) / G;
-        const int32_t q0 = g * per < na ? g * per : na;
+        const int32_t per = (na + parts - 1) / parts;
+        const int32_t q0 = gp * per < na ? gp * per : na;
         const int32_t q1 = q0 + per < na ? q0 + per : na;
         for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
             int32_t id[kLevelBatch];
@@ -779,12 +797,13 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
                     atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
         }
     }
-    level_barrier(L);
-    // workgroup g owns words [w0, w1) of the bitmap, thread t a contiguous
-    // run [wa, wb) of them
+    if (shared) level_barrier(L);
+    else __syncthreads();
+    // this workgroup owns words [w0, w1) of the bitmap, thread t a
+    // contiguous run [wa, wb) of them
     const int64_t nw = (L.n + 31) >> 5;
-    const int64_t wper = (nw + G - 1) / G;
-    const int64_t w0 = (int64_t)g * wper < nw ? (int64_t)g * wper : nw;
+    const int64_t wper = (nw + parts - 1) / parts;
+    const int64_t w0 = (int64_t)gp * wper < nw ? (int64_t)gp * wper : nw;
     const int64_t w1 = w0 + wper < nw ? w0 + wper : nw;
     const int64_t tper = (w1 - w0 + kWG - 1) / kWG;
     const int64_t wa = w0 + tid * tper < w1 ? w0 + tid * tper : w1;
@@ -792,11 +811,12 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     int32_t cnt = 0;
     for (int64_t w = wa; w < wb; ++w) cnt += __popc(L.bits[w]);
     int32_t wg_total;
-    const int32_t pre = block_exscan_i32(cnt, s_scan, &wg_total);
-    if (tid == 0) L.wg_hist[g * 64] = wg_total;
-    level_barrier(L);
-    int32_t pos = pre;
-    for (int w = 0; w < g; ++w) pos += L.wg_hist[w * 64];
+    int32_t pos = block_exscan_i32(cnt, s_scan, &wg_total);
+    if (shared) {
+        if (tid == 0) L.wg_hist[g * 64] = wg_total;
+        level_barrier(L);
+        for (int w = 0; w < g; ++w) pos += L.wg_hist[w * 64];
+    }
     int32_t* out = C == 1 ? L.perm : L.idx;
     int cn = 0, cur = 0;
     if (C > 1) {
@@ -823,11 +843,8 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             out[pos++] = i;
         }
     }
-    if (C == 1) {
-        if (g == 0) plan_body(sa, na);
-        return;
-    }
-    level_barrier(L);   // every cluster's first position is written
+    if (C > 1 && shared) level_barrier(L);   // every cluster's first position is written
+    else __syncthreads();
     if (g == 0) plan_body(sa, na);
 }
 
