@@ -700,13 +700,13 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     }
     __syncthreads();
     const int32_t na = s_na;
-    // Workgroups that list the block in ascending particle order (0: the
-    // block is used as the order's prefix, or, with clusters, grouped by a
-    // counting sort in LDS).  Ascending order pays on large blocks: a
-    // wave's particles then lie close together and fewer j-tiles need the
-    // self-pair mask.  One system lists a large block with every workgroup
-    // after a large block, with workgroup 0 alone (only above kLevelOrder)
-    // after a small one, when the others have already left.
+    // Workgroups that take part in listing the block (0: workgroup 0, and
+    // one system uses the order's prefix as it is).  With clusters the block
+    // is grouped by cluster, by all workgroups when large.  One system lists
+    // a large block in ascending particle order: a wave's particles then lie
+    // close together and fewer j-tiles need the self-pair mask; all
+    // workgroups do it after a large block, workgroup 0 alone (above
+    // kLevelOrder) after a small one, when the others have already left.
     int parts = 0;
     if (C == 1)
         parts = (r_big && na > kLevelLds) ? G : ((!r_big && na > kLevelOrder) ? 1 : 0);
@@ -721,88 +721,121 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         plan_body(sa, na);
         return;
     }
+    const bool shared = parts == G;
+    const int gp = shared ? g : 0;
     // After a shared re-sort the block's first na_prev positions are read
     // from the scratch (complete since the last barrier; the copy back to
-    // perm may still be under way).
+    // perm may still be under way).  A re-sort by workgroup 0 alone must be
+    // complete before the others read it.
     const int32_t split = r_big ? na_prev : 0;
+    if (shared && !r_big) level_barrier(L);
+    const int nparts = parts > 0 ? parts : 1;
+    const int32_t per = (na + nparts - 1) / nparts;
+    const int32_t q0 = gp * per < na ? gp * per : na;
+    const int32_t q1 = q0 + per < na ? q0 + per : na;
+
     if (C > 1) {
+        // 3. the block grouped by cluster (counting sort), with every
+        // cluster's first position and every position's cluster.  Small
+        // blocks are staged in LDS (na <= kLevelLds).
         for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
         for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
         __syncthreads();
-    }
-
-    if (parts == 0) {
-        // 3. a small block with clusters (workgroup 0): grouped by cluster
-        // (counting sort) with every cluster's first position and every
-        // position's cluster
-        for (int32_t p0 = 0; p0 < na; p0 += kStride) {
+        for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
             int32_t id[kLevelBatch];
             int b[kLevelBatch];
-            level_batch(L, na, p0, id, b, false, split);
+            level_batch(L, q1, p0, id, b, false, split);
 #pragma unroll
             for (int u = 0; u < kLevelBatch; ++u) {
                 const int32_t p = p0 + u * kWG + tid;
-                if (p < na) {
+                if (p < q1) {
                     const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                    s_id[p] = id[u];
-                    s_aux[p] = c;
+                    if (!shared) {
+                        s_id[p] = id[u];
+                        s_aux[p] = c;
+                    }
                     atomicAdd(&s_ch[c], 1);
                 }
             }
         }
         __syncthreads();
+        // thread t owns clusters [c0, c1): their totals, this workgroup's
+        // offset within each, and the clusters' first positions
         const int cper = (C + kWG - 1) / kWG;
         const int c0 = tid * cper < C ? tid * cper : C;
         const int c1 = c0 + cper < C ? c0 + cper : C;
+        if (shared) {
+            for (int c = c0; c < c1; ++c) L.wg_chist[g * kLdsClusters + c] = s_ch[c];
+            level_barrier(L);
+            for (int c = c0; c < c1; ++c) {
+                int32_t total = 0, before = 0;
+                for (int w = 0; w < G; ++w) {
+                    const int32_t v = L.wg_chist[w * kLdsClusters + c];
+                    total += v;
+                    before += w < g ? v : 0;
+                }
+                s_ch[c] = total;
+                s_aux[c] = before;
+            }
+            __syncthreads();
+        }
         int32_t loc = 0;
         for (int c = c0; c < c1; ++c) loc += s_ch[c];
         int32_t tot;
         int32_t run = block_exscan_i32(loc, s_scan, &tot);
         for (int c = c0; c < c1; ++c) {
             const int32_t k = s_ch[c];
-            s_ch[c] = run;
-            sa.act_start[c] = run;
+            s_ch[c] = run + (shared ? s_aux[c] : 0);
+            if (g == 0) sa.act_start[c] = run;
             run += k;
         }
         __syncthreads();
-        for (int32_t p = tid; p < na; p += kWG) {
-            const int c = s_aux[p];
-            const int32_t pos = atomicAdd(&s_ch[c], 1);
-            L.idx[pos] = s_id[p];
-            sa.act_cluster[pos] = c;
+        if (!shared) {
+            for (int32_t p = tid; p < na; p += kWG) {
+                const int c = s_aux[p];
+                const int32_t pos = atomicAdd(&s_ch[c], 1);
+                L.idx[pos] = s_id[p];
+                sa.act_cluster[pos] = c;
+            }
+        } else {
+            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+                int32_t id[kLevelBatch];
+                int b[kLevelBatch];
+                level_batch(L, q1, p0, id, b, false, split);
+#pragma unroll
+                for (int u = 0; u < kLevelBatch; ++u) {
+                    const int32_t p = p0 + u * kWG + tid;
+                    if (p < q1) {
+                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
+                        const int32_t pos = atomicAdd(&s_ch[c], 1);
+                        L.idx[pos] = id[u];
+                        sa.act_cluster[pos] = c;
+                    }
+                }
+            }
         }
         __syncthreads();
-        plan_body(sa, na);
+        if (g == 0) plan_body(sa, na);   // reads only workgroup 0's act_start
         return;
     }
 
-    // 3. a large block in ascending particle order, through a bitmap of the
-    // active particles (ascending order is also grouped by cluster).  One
-    // system rewrites the prefix of the order (its order within the prefix
-    // is free: the next re-sort reorders it).
-    const bool shared = parts > 1;
-    const int gp = shared ? g : 0;
-    if (shared && !r_big) level_barrier(L);   // workgroup 0's re-sort is complete
-    {
-        const int32_t per = (na + parts - 1) / parts;
-        const int32_t q0 = gp * per < na ? gp * per : na;
-        const int32_t q1 = q0 + per < na ? q0 + per : na;
-        for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-            int32_t id[kLevelBatch];
-            int b[kLevelBatch];
-            level_batch(L, q1, p0, id, b, false, split);
+    // 3. one system, a large block: ascending particle order through a
+    // bitmap of the active particles, written over the prefix of the order
+    // (its order within the prefix is free: the next re-sort reorders it)
+    for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+        int32_t id[kLevelBatch];
+        int b[kLevelBatch];
+        level_batch(L, q1, p0, id, b, false, split);
 #pragma unroll
-            for (int u = 0; u < kLevelBatch; ++u)
-                if (p0 + u * kWG + tid < q1)
-                    atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
-        }
+        for (int u = 0; u < kLevelBatch; ++u)
+            if (p0 + u * kWG + tid < q1) atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
     }
     if (shared) level_barrier(L);
     else __syncthreads();
     // this workgroup owns words [w0, w1) of the bitmap, thread t a
     // contiguous run [wa, wb) of them
     const int64_t nw = (L.n + 31) >> 5;
-    const int64_t wper = (nw + parts - 1) / parts;
+    const int64_t wper = (nw + nparts - 1) / nparts;
     const int64_t w0 = (int64_t)gp * wper < nw ? (int64_t)gp * wper : nw;
     const int64_t w1 = w0 + wper < nw ? w0 + wper : nw;
     const int64_t tper = (w1 - w0 + kWG - 1) / kWG;
@@ -817,34 +850,14 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         level_barrier(L);
         for (int w = 0; w < g; ++w) pos += L.wg_hist[w * 64];
     }
-    int32_t* out = C == 1 ? L.perm : L.idx;
-    int cn = 0, cur = 0;
-    if (C > 1) {
-        cn = lower_bound_i64(s_off, C, wa << 5);            // first cluster start >= 32 wa
-        cur = upper_bound_i64(s_off, C + 1, wa << 5) - 1;   // cluster of index 32 wa
-    }
     for (int64_t w = wa; w < wb; ++w) {
         uint32_t word = L.bits[w];
         L.bits[w] = 0u;
-        if (C > 1) {
-            while (cn < C && s_off[cn] < ((w + 1) << 5)) {
-                const int sh = (int)(s_off[cn] - (w << 5));
-                sa.act_start[cn] = pos + __popc(word & ((1u << sh) - 1u));
-                ++cn;
-            }
-        }
         while (word) {
-            const int32_t i = (int32_t)((w << 5) + __builtin_ctz(word));
+            L.perm[pos++] = (int32_t)((w << 5) + __builtin_ctz(word));
             word &= word - 1u;
-            if (C > 1) {
-                while (cur + 1 < C && s_off[cur + 1] <= i) ++cur;
-                sa.act_cluster[pos] = cur;
-            }
-            out[pos++] = i;
         }
     }
-    if (C > 1 && shared) level_barrier(L);   // every cluster's first position is written
-    else __syncthreads();
     if (g == 0) plan_body(sa, na);
 }
 
