@@ -221,9 +221,10 @@ hipError_t launch_level_count(const LevelArgs& L, hipStream_t st);
 hipError_t launch_level_build(const LevelArgs& L, hipStream_t st);
 // Re-sorts the previous block by its new steps, selects the next block,
 // groups it by cluster (C > 1; C <= kLdsClusters) and plans the sweep.
-// Blocks up to a few thousand particles take one workgroup; larger ones are
-// shared by kLevelGrid workgroups that meet at barriers (all of them are
-// resident at once: the kernel runs alone on the stream and needs little).
+// One system takes one workgroup.  With clusters, blocks up to a few
+// thousand particles take workgroup 0; larger ones are shared by
+// kLevelGrid workgroups that meet at barriers (all of them are resident at
+// once: the kernel runs alone on the stream and needs little).
 constexpr int kLevelGrid = 16;
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st);
 hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);

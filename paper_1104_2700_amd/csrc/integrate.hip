@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
 
 constexpr int kLevelLds = 2048;   // blocks handled by one workgroup, staged in LDS
 constexpr int kLevelBatch = 8;    // elements per thread whose loads are issued together
-constexpr int kLevelOrder = 8192; // one system: blocks workgroup 0 lists in particle order
+constexpr int kLevelOrder = 4096; // one system: blocks listed in particle order
 
 // Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of the
 // order (positions below `split` from the re-sort scratch L.tmp, the rest
@@ -495,7 +495,7 @@ __device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int
 __device__ void level_barrier(const LevelArgs& L)
 {
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (gridDim.x > 1 && threadIdx.x == 0) {
         uint32_t* count = L.bar;
         uint32_t* gen = L.bar + 1;
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -702,14 +702,13 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     const int32_t na = s_na;
     // Workgroups that take part in listing the block (0: workgroup 0, and
     // one system uses the order's prefix as it is).  With clusters the block
-    // is grouped by cluster, by all workgroups when large.  One system lists
-    // a large block in ascending particle order: a wave's particles then lie
-    // close together and fewer j-tiles need the self-pair mask; all
-    // workgroups do it after a large block, workgroup 0 alone (above
-    // kLevelOrder) after a small one, when the others have already left.
+    // is grouped by cluster, by all workgroups when large.  One system (one
+    // workgroup) lists a block above kLevelOrder in ascending particle
+    // order: a wave's particles then lie close together and fewer j-tiles
+    // need the self-pair mask.
     int parts = 0;
     if (C == 1)
-        parts = (r_big && na > kLevelLds) ? G : ((!r_big && na > kLevelOrder) ? 1 : 0);
+        parts = na > kLevelOrder ? G : 0;
     else
         parts = na > kLevelLds ? G : 0;
     if (na == 0) {
@@ -1149,7 +1148,11 @@ hipError_t launch_level_build(const LevelArgs& L, hipStream_t st)
 
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st)
 {
-    hipLaunchKernelGGL(level_select_kernel, dim3(kLevelGrid), dim3(kWG), 0, st, L, sa);
+    // one system: one workgroup (a grid over every XCD costs about 1.4 us
+    // per step even when the others leave at once, and the shared re-sort
+    // of large blocks did not pay for one system); clusters: kLevelGrid
+    const int grid = sa.n_clusters > 1 ? kLevelGrid : 1;
+    hipLaunchKernelGGL(level_select_kernel, dim3(grid), dim3(kWG), 0, st, L, sa);
     return hipGetLastError();
 }
 
