@@ -487,7 +487,9 @@ int hermite_destroy(hermite_ctx* c)
     Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
                    &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
-                   &c->ticket, &c->flag};
+                   &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
+                   &c->lvl_cursor, &c->lvl_misc, &c->lvl_wg, &c->lvl_wgc, &c->lvl_bar,
+                   &c->lvl_bits};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
