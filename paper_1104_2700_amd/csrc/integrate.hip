@@ -537,7 +537,9 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
     const bool r_big = na_prev > kLevelLds;
-    // one system after a small block: workgroup 0 does everything
+    // One system is launched as one workgroup; were it given more, they
+    // would have nothing to do after a small block (nothing is posted for
+    // them to wait on).
     if (g > 0 && C == 1 && !r_big) return;
     if (tid < 64) {
         s_hist[tid] = 0;
