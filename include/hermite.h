@@ -255,10 +255,11 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
  * kernel) instead of scanning t and dt; otherwise, and for one system of
  * n <= 2048 (selected inside the sweep) or more than 2048 clusters, the
  * run selects as hermite_step does.  Both give the same state bit for bit.
- * Large blocks are shared by 16 workgroups that wait for each other with
- * bounded waits; should a wait run out (the workgroups could not run at
- * the same time, e.g. a device filled by other work), the call returns
- * HERMITE_EHIP with a message and the state is not to be trusted.
+ * With clusters, large blocks are shared by 16 workgroups that wait for
+ * each other with bounded waits; should a wait run out (the workgroups
+ * could not run at the same time, e.g. a device filled by other work), the
+ * call returns HERMITE_EHIP with a message and the state is not to be
+ * trusted.
  *
  * steps_out / interactions_out (host, may be NULL) receive the block-step
  * count and the number of pair interactions (sum over steps of
