@@ -152,6 +152,9 @@ struct CorrectArgs {
     int64_t* counters;         // [2] += clamped, or null
     int predict_i;             // 1: predict the active particle from x, v, a, j, t
                                //    at T instead of reading xp, vp
+    int32_t* na_seen;          // or null: receives n_act (a run's selection reads the
+                               // previous block's size from here, never from a word it
+                               // rewrites itself)
 };
 
 hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
@@ -205,6 +208,9 @@ struct LevelArgs {
     uint32_t* bar;       // [4] workgroup barrier: arrivals, generation; [2], [3]
                          // n_act posted by workgroup 0 and its readers (all
                          // zeroed once, left zero)
+    int32_t* na_prev;    // the previous block's n_act, written by the corrector
+                         // (*na is rewritten by workgroup 0 while the others may
+                         // still be starting)
     uint32_t* bits;      // [(n + 31) / 32] active-particle bitmap (zeroed once, left zero)
     int64_t T_end;
     int32_t* na;         // n_act: the previous step's in, this step's out

@@ -279,6 +279,7 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_dt_pa
     L.wg_hist = (int32_t*)c->lvl_wg.p;
     L.wg_chist = (int32_t*)c->lvl_wgc.p;
     L.bar = (uint32_t*)c->lvl_bar.p;
+    L.na_prev = (int32_t*)c->lvl_bar.p + 4;
     L.bits = (uint32_t*)c->lvl_bits.p;
     L.T_end = T_end;
     L.na = (int32_t*)c->step_na.p;
@@ -302,15 +303,19 @@ int level_init(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* 
     CHECK(ensure(c, c->lvl_misc, sizeof(int64_t) * 8));
     CHECK(ensure(c, c->lvl_wg, sizeof(int32_t) * kLevelGrid * 64));
     CHECK(ensure(c, c->lvl_wgc, sizeof(int32_t) * kLevelGrid * kLdsClusters));
-    CHECK(ensure(c, c->lvl_bar, sizeof(uint32_t) * 4));
+    CHECK(ensure(c, c->lvl_bar, sizeof(uint32_t) * 8));
     CHECK(ensure(c, c->lvl_bits, sizeof(uint32_t) * ((s->n + 31) / 32)));
     const LevelArgs L = level_args(c, s, p, 0);
     const int64_t init[8] = {0, INT64_MIN, INT64_MAX, 0, 0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(L.misc, init, sizeof init, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * 64, st));
     HIP_OK(hipMemsetAsync(L.cursor, 0, sizeof(int32_t) * 64, st));
-    HIP_OK(hipMemsetAsync(L.bar, 0, sizeof(uint32_t) * 4, st));
+    HIP_OK(hipMemsetAsync(L.bar, 0, sizeof(uint32_t) * 8, st));
     HIP_OK(hipMemsetAsync(L.bits, 0, sizeof(uint32_t) * ((s->n + 31) / 32), st));
+    // every entry of the active list and its clusters holds a valid index
+    // from the start, whatever a step writes
+    HIP_OK(hipMemsetAsync(c->step_idx.p, 0, sizeof(int32_t) * s->n, st));
+    HIP_OK(hipMemsetAsync(c->step_acl.p, 0, sizeof(int32_t) * s->n, st));
     HIP_OK(launch_level_count(L, st));
     int64_t h[4];
     HIP_OK(hipMemcpyAsync(h, L.misc, sizeof h, hipMemcpyDeviceToHost, st));
@@ -409,6 +414,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.k_max = p->k_max;
     ca.counters = counters;
     ca.predict_i = 1;
+    if (level) ca.na_seen = (int32_t*)c->lvl_bar.p + 4;
     HIP_OK(launch_correct_reduce(ca, a, st));
     return HERMITE_OK;
 }
@@ -824,9 +830,12 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
                                   hipMemcpyDeviceToHost, st));
         int bad = 0;
         CHECK(check_finite(c, s, st, &bad));   // synchronises st
-        if (timeout)
+        if (timeout == 1)
             return fail(HERMITE_EHIP, "block selection: a workgroup barrier timed out "
                         "(workgroups not resident together)");
+        if (timeout)
+            return fail(HERMITE_EHIP, "block selection: inconsistent step-size order "
+                        "(a position out of range was not written)");
         if (bad)
             return fail(HERMITE_ENONFINITE,
                         "non-finite state after block time %lld ticks (e.g. coincident "

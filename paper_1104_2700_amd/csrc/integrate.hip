@@ -458,6 +458,7 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
     if (blockIdx.x == 0 && tid == 0) {
         L.misc[0] = L.misc[1];
         *L.na = 0;
+        *L.na_prev = 0;
     }
 }
 
@@ -487,6 +488,19 @@ __device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int
 #pragma unroll
         for (int u = 0; u < kLevelBatch; ++u) b[u] = log2_step(d[u]);
     }
+}
+
+// out[pos] = v when 0 <= pos < cnt; otherwise records the inconsistency in
+// misc[4] (reported by hermite_run) instead of writing out of range.
+__device__ __forceinline__ bool level_put(const LevelArgs& L, int32_t* out, int32_t pos,
+                                          int32_t cnt, int32_t v)
+{
+    if (pos >= 0 && pos < cnt) {
+        out[pos] = v;
+        return true;
+    }
+    __hip_atomic_store(&L.misc[4], (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
 }
 
 // Barrier of all workgroups of the selection (every one calls it at the
@@ -533,7 +547,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     const int tid = threadIdx.x;
     const int G = gridDim.x, g = blockIdx.x;
     const int C = sa.n_clusters;
-    const int32_t na_prev = *L.na;
+    const int32_t na_prev = *L.na_prev;
     const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
     const bool r_big = na_prev > kLevelLds;
@@ -582,7 +596,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             }
             __syncthreads();
             for (int32_t p = tid; p < na_prev; p += kWG)
-                s_aux[atomicAdd(&s_cur[s_lv[p]], 1)] = s_id[p];
+                level_put(L, s_aux, atomicAdd(&s_cur[s_lv[p]], 1), na_prev, s_id[p]);
             __syncthreads();
             for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
         } else {
@@ -624,7 +638,8 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
                 level_batch(L, q1, p0, id, b, true);
 #pragma unroll
                 for (int u = 0; u < kLevelBatch; ++u)
-                    if (p0 + u * kWG + tid < q1) L.tmp[atomicAdd(&s_cur[b[u]], 1)] = id[u];
+                    if (p0 + u * kWG + tid < q1)
+                        level_put(L, L.tmp, atomicAdd(&s_cur[b[u]], 1), na_prev, id[u]);
             }
             level_barrier(L);
             for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
@@ -795,8 +810,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             for (int32_t p = tid; p < na; p += kWG) {
                 const int c = s_aux[p];
                 const int32_t pos = atomicAdd(&s_ch[c], 1);
-                L.idx[pos] = s_id[p];
-                sa.act_cluster[pos] = c;
+                if (level_put(L, L.idx, pos, na, s_id[p])) sa.act_cluster[pos] = c;
             }
         } else {
             for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
@@ -809,8 +823,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
                     if (p < q1) {
                         const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
                         const int32_t pos = atomicAdd(&s_ch[c], 1);
-                        L.idx[pos] = id[u];
-                        sa.act_cluster[pos] = c;
+                        if (level_put(L, L.idx, pos, na, id[u])) sa.act_cluster[pos] = c;
                     }
                 }
             }
@@ -855,7 +868,7 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
         uint32_t word = L.bits[w];
         L.bits[w] = 0u;
         while (word) {
-            L.perm[pos++] = (int32_t)((w << 5) + __builtin_ctz(word));
+            level_put(L, L.perm, pos++, na, (int32_t)((w << 5) + __builtin_ctz(word)));
             word &= word - 1u;
         }
     }
@@ -984,6 +997,7 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
 __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, SweepArgs sa)
 {
     const int na = sa.plan->n_act;
+    if (c.na_seen && blockIdx.x == 0 && threadIdx.x == 0) *c.na_seen = na;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     if (thread_reduce(sa.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
