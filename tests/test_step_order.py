@@ -72,3 +72,43 @@ def test_rule_needs_the_grid_condition():
     assert T == 5 and list(idx) == [0]
     T_last = int(t.max())
     assert (T_last // 4 + 1) * 4 == 4 != T
+
+
+@pytest.mark.parametrize("seed,n,k_min,k_max", [(5, 300, 2, 14), (6, 2000, 0, 20)])
+def test_order_kept_by_resorting_the_block_only(seed, n, k_min, k_max):
+    """The structure a run keeps: a permutation by step size and a count per
+    step size.  Each step only the previous block (a prefix) is re-sorted by
+    its new steps, and the counts of the step sizes that were active are
+    replaced by the block's new counts; the order stays sorted, the counts
+    stay exact, and every block the oracle selects is the prefix of the
+    size the counts give."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(k_min, k_max + 1, size=n)
+    dt = (np.int64(1) << (TB - k)).astype(np.int64)
+    t = np.zeros(n, dtype=np.int64)
+    b = np.log2(dt).astype(int)
+    perm = np.argsort(b, kind="stable")
+    cnt = np.bincount(b, minlength=64)
+    T_last, na_prev, T_prev = 0, 0, 0
+    for _ in range(300):
+        if na_prev > 0:
+            z = (T_prev & -T_prev).bit_length() - 1
+            blk = perm[:na_prev]
+            nb = np.log2(dt[blk]).astype(int)
+            perm[:na_prev] = blk[np.argsort(nb, kind="stable")]
+            cnt[:z + 1] = 0
+            cnt += np.bincount(nb, minlength=64)
+            T_last = T_prev
+        bl = np.log2(dt).astype(int)
+        assert np.all(np.diff(bl[perm]) >= 0)
+        assert np.array_equal(cnt, np.bincount(bl, minlength=64))
+        bmin = int(np.nonzero(cnt)[0][0])
+        T = ((T_last >> bmin) + 1) << bmin
+        z = (T & -T).bit_length() - 1
+        na = int(cnt[:z + 1].sum())
+        T_o, idx = O.select(t, dt)
+        assert T == T_o and np.array_equal(np.sort(perm[:na]), idx)
+        k_new = _quantised_steps(rng, T, TB - bl[idx], k_min, k_max)
+        t[idx] = T
+        dt[idx] = np.int64(1) << (TB - k_new)
+        na_prev, T_prev = na, T
