@@ -70,8 +70,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sweep's sharding is described in DESIGN.md); run with --gpus 1.",
+        print("bench.py measures one GPU only: the library runs on one GPU (the sweep "
+              "would shard over GPUs by splitting the j range, each GPU summing its "
+              "share for every active particle); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     import torch
