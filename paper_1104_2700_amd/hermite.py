@@ -284,7 +284,9 @@ class Context:
             sync_every=64, clusters=None, max_steps=0, stream=None, with_done=False):
         """Integrate to T_end ticks (or max_steps launched steps); returns
         (block steps, interactions) and, with ``with_done``, whether every
-        particle reached T_end."""
+        particle reached T_end.  Raises HermiteError with ENONFINITE for a
+        non-finite state, or EHIP if the block selection reports a timed-out
+        workgroup wait or an inconsistent step-size order."""
         steps, inter, done = _i64(0), _i64(0), _i32(0)
         _check(lib.hermite_run(self.h, ctypes.byref(s.c()), _cl(clusters), float(eps2),
                                int(precision), ctypes.byref(params), int(T_end),
