@@ -54,15 +54,18 @@ extern "C" {
 /* Section 3.2 precision split, modified: relative position and velocity  */
 /* subtracted in FP64, cast to FP32 for the pair arithmetic (r^2 + eps^2, */
 /* rsqrt, jerk and potential terms), partial sums over short runs of j in */
-/* FP32 and the running sums of acc, jerk and pot in FP64.                */
+/* FP32 and the running sums of acc, jerk and pot in FP64.  Near pairs,   */
+/* and small systems altogether, are evaluated in FP64 (see              */
+/* hermite_set_mixed_policy).                                             */
 #define HERMITE_MIXED     1
 /* As HERMITE_MIXED, but the running sums are two-float (FP32 hi + lo,    */
 /* compensated by TwoSum) instead of FP64.                                */
 #define HERMITE_MIXED_2F  2
 /* Section 3.2 precision split as printed: FP64 relative position, FP32   */
 /* velocities and FP32 velocity difference, FP32 pair arithmetic, FP64    */
-/* sums of acc and pot, and the jerk summed in FP32 (over each j-chunk;   */
-/* chunk sums are added in FP64).                                         */
+/* sums of acc and pot, and the jerk summed in FP32: one running sum per  */
+/* lane over every L-th j of the whole system (no j-split across work     */
+/* items in this mode), the L lanes' sums added in FP32.                  */
 #define HERMITE_MIXED_SP  3
 
 /* ---- timestep criterion forms (Section 2, eq. (timestep)) ------------ */
@@ -280,8 +283,9 @@ int hermite_check_finite(hermite_ctx* ctx, const hermite_state* s, void* stream)
 /* Cumulative device counters since creation (synchronises `stream`):
  * out[0] block steps, out[1] interactions, out[2] clamped steps,
  * out[3] block time T and out[4] n_act of the last step that had active
- * particles. */
-int hermite_counters(hermite_ctx* ctx, int64_t out[5], void* stream);
+ * particles, out[5] particles whose mixed-precision sums were refined in
+ * FP64 (see hermite_set_mixed_policy). */
+int hermite_counters(hermite_ctx* ctx, int64_t out[6], void* stream);
 
 /* Histogram of the active-block sizes of every block step since creation
  * (synchronises `stream`): out[b] for b >= 1 counts steps with
@@ -292,6 +296,38 @@ int hermite_block_histogram(hermite_ctx* ctx, int64_t out[33], void* stream);
 /* ---- launch shape and autotuner ------------------------------------------ */
 
 int hermite_get_tuning(hermite_ctx* ctx, int precision, hermite_tuning* out);
+
+/* Mixed-precision policy of HERMITE_MIXED, HERMITE_MIXED_2F and
+ * HERMITE_MIXED_SP (Section 3.2's split of the pair arithmetic).
+ *
+ * Near field.  With FP32 pair terms, the error of a particle's sum is a
+ * random walk of per-term errors of a few u32 weighted by the terms'
+ * magnitudes, so it is led by its nearest pairs.  Pairs with
+ * |r| < near_factor * N_c^(-1/3) (N_c the size of the particle's system;
+ * in standard N-body units about near_factor mean interparticle spacings
+ * of a Plummer core) are summed in FP64 from the same FP64 positions,
+ * velocities and masses.  With 0 only the self pair and coincident
+ * particles take the FP64 path.
+ *
+ * FP64 systems.  Systems (the state, or clusters) of fewer than
+ * fp64_below particles are swept in FP64 altogether: at those sizes the
+ * FP64 sweep is as fast as the FP32 one and exact.
+ *
+ * Refinement.  HERMITE_MIXED and HERMITE_MIXED_2F also estimate each
+ * particle's remaining FP32 error from its sums (the squares of the FP32
+ * partial sums over runs of 16 j) and sum a particle again in FP64 when
+ * the estimate exceeds 4e-8 of its acceleration or jerk: particles whose
+ * sums almost cancel.  The count is reported by hermite_counters.
+ *
+ * Defaults: near_factor 3, fp64_below 8192 for HERMITE_MIXED and
+ * HERMITE_MIXED_2F; 0 and 0 for HERMITE_MIXED_SP (the scheme as printed).
+ * EINVAL for HERMITE_FP64, a negative, infinite or NaN near_factor, a
+ * negative fp64_below, or fp64_below != 0 for HERMITE_MIXED_SP.  Setting
+ * the policy drops captured step graphs. */
+int hermite_set_mixed_policy(hermite_ctx* ctx, int precision, double near_factor,
+                             int64_t fp64_below);
+int hermite_get_mixed_policy(hermite_ctx* ctx, int precision, double* near_factor,
+                             int64_t* fp64_below);
 int hermite_set_tuning(hermite_ctx* ctx, int precision,
                        const hermite_tuning* in);
 

@@ -13,8 +13,13 @@ constexpr int kWG = 256;
 constexpr int kTJ = 256;
 
 // Device counters: [0] block steps, [1] interactions, [2] clamped steps,
-// [3] last block time, [4] last n_act, [kHistBase + b] block-size histogram.
+// [3] last block time, [4] last n_act, [5] particles refined in FP64 by a
+// mixed sweep, [kHistBase + b] block-size histogram.
 constexpr int kHistBase = 8;
+
+// Rows of the sweep's partial sums per (j-chunk, active particle): acc xyz,
+// jerk xyz, -pot, and the packed FP32 error estimates of the mixed paths.
+constexpr int kRows = 8;
 constexpr int kCounters = kHistBase + 33;
 
 // Shape of one force sweep, decided on the device from the active count
@@ -59,6 +64,26 @@ struct SweepArgs {
     int32_t target_lanes;
     int32_t min_j_per_lane;
     int32_t ipl;               // active particles per lane (set by launch_force)
+    int32_t one_chunk;         // nonzero: no j-split across work items (the
+                               // paper-faithful mode's FP32 jerk sums span all j)
+    // mixed precisions: pairs closer than near_factor * N_c^(-1/3) (N_c the
+    // size of the particle's system) are summed in FP64, and systems with
+    // N_c < fp64_below are swept in FP64 altogether
+    double near_factor;
+    int64_t fp64_below;
+    // nonzero: the reduce stage flags particles whose estimated mixed
+    // error is too large (ref_pos[p] = 1) and plans their FP64 refinement
+    int32_t refine;
+    int32_t* ref_pos;          // [n_act_max] a flagged position's slot in the list, or -1
+    int32_t* ref_idx;          // [n_act_max] flagged particles (the refine sweep's idx)
+    int32_t* ref_p;            // [n_act_max] their active positions
+    int32_t* ref_tmp;          // [n_act_max] flagged positions, compacted per reduce unit
+    int32_t* ref_ucnt;         // [n_act_max / 4 + 1] flagged per reduce unit, then its first slot
+    int32_t* ref_ccnt;         // [C] flagged per cluster, then placement cursors
+    // items a sweep launch takes: 0 all; 1 those of systems with
+    // N_c >= fp64_below (the mixed kernel of a mixed ensemble sweep); 2 those
+    // with N_c < fp64_below (its FP64 kernel)
+    int32_t kind;
     // counters (may be null): [0] steps, [1] interactions, [4] last n_act
     int64_t* counters;
     // On-the-fly prediction (block-step path): when pred_x is non-null the
@@ -106,8 +131,17 @@ inline int reduce_grid(int64_t n_act_max)
 // variant bit 0: two active particles per lane (else one); bit 1: split
 // FP32 hi/lo differences in the mixed precisions.
 // pot_only: the energy sweep (FP64, potential only).
-hipError_t launch_force(const SweepArgs& a, int precision, int variant,
+// ra (or null): the refine sweep of a mixed sweep with refinement (a.refine):
+// the reduce flags and plans, the FP64 refine sweep runs, and the refined
+// sums are scattered into the outputs.
+hipError_t launch_force(const SweepArgs& a, const SweepArgs* ra, int precision, int variant,
                         int grid, bool pot_only, hipStream_t st);
+
+// Block-step form of the refinement: the flagging reduce into the compact
+// outputs a.acc / a.jerk / a.pot, then the FP64 refine sweep (the corrector,
+// launch_correct_refine, takes the refined sums of flagged positions).
+hipError_t launch_reduce_refine(const SweepArgs& a, const SweepArgs& ra, int variant, int grid,
+                                hipStream_t st);
 
 // Block selection (integrate.hip).
 // Number of select blocks (size of block_min / block_cnt) for n particles.
@@ -158,6 +192,7 @@ struct CorrectArgs {
 };
 
 hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
+hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& ra, hipStream_t st);
 
 // Fused block-step stages: selection and the sweep plan in two launches
 // (prediction is folded into the sweep and the corrector), and the

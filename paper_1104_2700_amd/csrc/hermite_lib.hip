@@ -70,8 +70,14 @@ struct hermite_ctx {
     std::string arch;
     hipStream_t cap_stream = nullptr;
     hermite_tuning tuning[4];
+    double near_factor[4];     // near-field radius factor per precision
+    int64_t fp64_below[4];     // systems smaller than this are swept in FP64
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
+    // refinement of mixed sweeps: flags and lists, the refine sweep's plan,
+    // per-cluster tables and partial sums, and the flagging reduce's ticket
+    Buf ref_pos, ref_idx, ref_p, ref_tmp, ref_ucnt, ref_ccnt, rplan, ract_start, ract_cnt,
+        rchunks, ritem_off, rpartial;
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
@@ -191,10 +197,31 @@ hermite_tuning default_tuning(const hermite_ctx* c, int precision)
     return t;
 }
 
+// Mixed-precision policy (hermite_set_mixed_policy).  Near-field radius
+// factor, in N_c^(-1/3) (about one mean interparticle spacing of a Plummer
+// core in standard units): the FP32 pair error of a particle is led by its
+// nearest pairs, whose terms are the largest, so HERMITE_MIXED and
+// HERMITE_MIXED_2F sum the pairs within this radius in FP64.  Systems
+// smaller than fp64_below are swept in FP64 altogether: below about 10^4
+// particles the FP64 sweep takes no longer than the FP32 one with its near
+// field (MI355X: 0.020 / 0.020 ms at N = 1024, 0.042 / 0.049 ms at 4096,
+// 0.33 / 0.32-0.36 ms at 16384; 5.1 / 4.0 ms at 65536).  The paper-faithful
+// mode keeps the printed scheme: radius 0 (only the self pair and
+// coincident particles take the FP64 path) and no FP64 systems.
+double default_near_factor(int precision)
+{
+    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 3.0 : 0.0;
+}
+
+int64_t default_fp64_below(int precision)
+{
+    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 8192 : 0;
+}
+
 // Fills the sweep arguments and makes sure the scratch they point to exists.
 int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
                   const double* xp, const double* vp, const int32_t* idx,
-                  const int32_t* n_act_dev, int32_t n_act_max, double eps2,
+                  const int32_t* n_act_dev, int32_t n_act_max, double eps2, int precision,
                   const hermite_tuning& tu, double* acc, double* jerk, double* pot,
                   SweepArgs* a)
 {
@@ -204,7 +231,7 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     CHECK(ensure(c, c->act_cnt, sizeof(int32_t) * C));
     CHECK(ensure(c, c->chunks, sizeof(int32_t) * C));
     CHECK(ensure(c, c->item_off, sizeof(int32_t) * (C + 1)));
-    const int64_t cap = (int64_t)7 * 32 * std::max<int64_t>(n_act_max, 4096);
+    const int64_t cap = (int64_t)kRows * 32 * std::max<int64_t>(n_act_max, 4096);
     CHECK(ensure(c, c->partial, sizeof(double) * cap));
     CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
     std::memset(a, 0, sizeof *a);
@@ -229,6 +256,27 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     a->partial_cap = (int64_t)(c->partial.bytes / sizeof(double));
     a->target_lanes = tu.target_lanes;
     a->min_j_per_lane = tu.min_j_per_lane;
+    a->near_factor = precision == HERMITE_FP64 ? 0.0 : c->near_factor[precision];
+    a->fp64_below = precision == HERMITE_FP64 ? 0 : c->fp64_below[precision];
+    // refinement for the mixed precisions that sweep some system in FP32
+    a->refine = ((precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) &&
+                 a->n_cmax >= a->fp64_below) ? 1 : 0;
+    if (a->refine) {
+        const size_t na = (size_t)std::max<int32_t>(n_act_max, 1);
+        CHECK(ensure(c, c->ref_pos, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_idx, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_p, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_tmp, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_ucnt, sizeof(int32_t) * (na / (kWG / 64) + 1)));
+        CHECK(ensure(c, c->ref_ccnt, sizeof(int32_t) * (size_t)C));
+        a->ref_pos = (int32_t*)c->ref_pos.p;
+        a->ref_idx = (int32_t*)c->ref_idx.p;
+        a->ref_p = (int32_t*)c->ref_p.p;
+        a->ref_tmp = (int32_t*)c->ref_tmp.p;
+        a->ref_ucnt = (int32_t*)c->ref_ucnt.p;
+        a->ref_ccnt = (int32_t*)c->ref_ccnt.p;
+    }
+    a->one_chunk = precision == HERMITE_MIXED_SP ? 1 : 0;
     a->counters = (int64_t*)c->counters.p;
     a->acc = acc;
     a->jerk = jerk;
@@ -236,11 +284,55 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     return HERMITE_OK;
 }
 
+// The FP64 refine sweep of a mixed sweep with refinement: the same system
+// and prediction, the flagged particles (ref_idx) as its active list, and
+// scratch of its own (its plan is made on the device by the flagging
+// reduce).  Its partial-sum buffer holds at least four chunks for every
+// active particle.
+int prepare_refine(hermite_ctx* c, const SweepArgs& a, SweepArgs* ra)
+{
+    const int C = a.n_clusters;
+    CHECK(ensure(c, c->rplan, sizeof(SweepPlan)));
+    CHECK(ensure(c, c->ract_start, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->ract_cnt, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->rchunks, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->ritem_off, sizeof(int32_t) * (C + 1)));
+    const int64_t cap = (int64_t)kRows * 4 * std::max<int64_t>(a.n_act_max, 4096);
+    CHECK(ensure(c, c->rpartial, sizeof(double) * cap));
+    *ra = a;
+    ra->idx = a.ref_idx;
+    ra->n_act_dev = nullptr;
+    ra->plan = (SweepPlan*)c->rplan.p;
+    ra->act_start = (int32_t*)c->ract_start.p;
+    ra->act_cnt = (int32_t*)c->ract_cnt.p;
+    ra->chunks = (int32_t*)c->rchunks.p;
+    ra->item_off = (int32_t*)c->ritem_off.p;
+    ra->act_cluster = nullptr;
+    // with clusters the flagging reduce writes each cluster's run start
+    ra->sel_clusters = C > 1 ? 1 : 0;
+    ra->partial = (double*)c->rpartial.p;
+    ra->partial_cap = (int64_t)(c->rpartial.bytes / sizeof(double));
+    ra->refine = 0;
+    ra->near_factor = 0.0;
+    ra->fp64_below = 0;
+    ra->kind = 0;
+    ra->counters = nullptr;
+    ra->sel_dt = nullptr;
+    ra->sel_idx_out = nullptr;
+    ra->sel_na_out = nullptr;
+    ra->sel_T_out = nullptr;
+    ra->acc = ra->jerk = ra->pot = nullptr;
+    return HERMITE_OK;
+}
+
 int run_force(hermite_ctx* c, const SweepArgs& a, int precision, const hermite_tuning& tu,
               bool pot_only, hipStream_t st)
 {
     const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
-    HIP_OK(launch_force(a, precision, tu.variant, grid, pot_only, st));
+    SweepArgs ra;
+    if (a.refine && !pot_only) CHECK(prepare_refine(c, a, &ra));
+    HIP_OK(launch_force(a, (a.refine && !pot_only) ? &ra : nullptr, precision, tu.variant, grid,
+                        pot_only, st));
     return HERMITE_OK;
 }
 
@@ -346,7 +438,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     int32_t* aidx = (level && !cl) ? (int32_t*)c->lvl_perm.p : idx;
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[precision];
-    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, aidx, na, (int32_t)n, eps2, tu, out,
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, aidx, na, (int32_t)n, eps2, precision, tu, out,
                         out + 3 * n, out + 6 * n, &a));
     a.ipl = (tu.variant & 1) ? 2 : 1;
     // with clusters the selection records the active runs and clusters
@@ -415,7 +507,19 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.counters = counters;
     ca.predict_i = 1;
     if (level) ca.na_seen = (int32_t*)c->lvl_bar.p + 4;
-    HIP_OK(launch_correct_reduce(ca, a, st));
+    if (a.refine) {
+        // mixed sums into the compact outputs with their error flags, the
+        // FP64 refine sweep of the flagged particles, then the corrector
+        SweepArgs ra;
+        CHECK(prepare_refine(c, a, &ra));
+        HIP_OK(launch_reduce_refine(a, ra, tu.variant, grid, st));
+        ca.acc1 = out;
+        ca.jrk1 = out + 3 * n;
+        ca.pot1 = out + 6 * n;
+        HIP_OK(launch_correct_refine(ca, ra, st));
+    } else {
+        HIP_OK(launch_correct_reduce(ca, a, st));
+    }
     return HERMITE_OK;
 }
 
@@ -472,7 +576,11 @@ int hermite_create(int device, hermite_ctx** out)
         delete c;
         return fail(HERMITE_EHIP, "hipStreamCreateWithFlags failed");
     }
-    for (int p = 0; p < 4; ++p) c->tuning[p] = default_tuning(c, p);
+    for (int p = 0; p < 4; ++p) {
+        c->tuning[p] = default_tuning(c, p);
+        c->near_factor[p] = default_near_factor(p);
+        c->fp64_below[p] = default_fp64_below(p);
+    }
     int rc = ensure(c, c->counters, sizeof(int64_t) * kCounters);
     if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * kCounters) != hipSuccess)
         rc = fail(HERMITE_EHIP, "hipMemset of counters failed");
@@ -491,7 +599,10 @@ int hermite_destroy(hermite_ctx* c)
     (void)hipDeviceSynchronize();
     drop_graphs(c);
     Buf* bufs[] = {&c->plan, &c->act_start, &c->act_cnt, &c->chunks, &c->item_off,
-                   &c->partial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
+                   &c->partial, &c->ref_pos, &c->ref_idx, &c->ref_p, &c->ref_tmp,
+                   &c->ref_ucnt, &c->ref_ccnt,
+                   &c->rplan, &c->ract_start, &c->ract_cnt, &c->rchunks, &c->ritem_off,
+                   &c->rpartial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
                    &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
                    &c->lvl_cursor, &c->lvl_misc, &c->lvl_wg, &c->lvl_wgc, &c->lvl_bar,
@@ -554,7 +665,7 @@ int hermite_force_jerk(hermite_ctx* c, const hermite_state* s, const hermite_clu
     if (!acc || !jerk) return fail(HERMITE_EINVAL, "null output pointer");
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[precision];
-    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, tu, acc,
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, precision, tu, acc,
                         jerk, pot, &a));
     return run_force(c, a, precision, tu, false, (hipStream_t)stream);
 }
@@ -629,7 +740,7 @@ int hermite_initialize(hermite_ctx* c, const hermite_state* s, const hermite_clu
     HIP_OK(launch_copy2(3 * s->n, s->x, s->xp, s->v, s->vp, st));
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[precision];
-    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, nullptr, nullptr, (int32_t)s->n, eps2, tu,
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, nullptr, nullptr, (int32_t)s->n, eps2, precision, tu,
                         s->a, s->j, s->pot, &a));
     CHECK(run_force(c, a, precision, tu, false, st));
     HIP_OK(launch_init_dt(s->n, s->tick_bits, s->a, s->j, s->t, s->dt, p->eta, p->form,
@@ -650,7 +761,7 @@ int hermite_energy(hermite_ctx* c, const hermite_state* s, const hermite_cluster
     double* phi = (double*)c->phi.p;
     SweepArgs a;
     const hermite_tuning& tu = c->tuning[HERMITE_FP64];
-    CHECK(prepare_sweep(c, s, cl, s->x, s->v, nullptr, nullptr, (int32_t)s->n, eps2, tu,
+    CHECK(prepare_sweep(c, s, cl, s->x, s->v, nullptr, nullptr, (int32_t)s->n, eps2, HERMITE_FP64, tu,
                         phi, nullptr, phi, &a));
     a.counters = nullptr;
     CHECK(run_force(c, a, HERMITE_FP64, tu, true, st));
@@ -689,8 +800,10 @@ static int launch_steps(hermite_ctx* c, const hermite_state* s, const hermite_cl
         SweepArgs a;
         double* out = (double*)c->step_out.p;
         CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, (int32_t*)c->step_idx.p,
-                            (int32_t*)c->step_na.p, (int32_t)s->n, eps2,
+                            (int32_t*)c->step_na.p, (int32_t)s->n, eps2, precision,
                             c->tuning[precision], out, out + 3 * s->n, out + 6 * s->n, &a));
+        SweepArgs ra;
+        if (a.refine) CHECK(prepare_refine(c, a, &ra));
     }
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) {
@@ -760,7 +873,7 @@ int hermite_check_finite(hermite_ctx* c, const hermite_state* s, void* stream)
     return HERMITE_OK;
 }
 
-int hermite_counters(hermite_ctx* c, int64_t out[5], void* stream)
+int hermite_counters(hermite_ctx* c, int64_t out[6], void* stream)
 {
     CHECK(check_ctx(c));
     if (!out) return fail(HERMITE_EINVAL, "null output pointer");
@@ -768,7 +881,7 @@ int hermite_counters(hermite_ctx* c, int64_t out[5], void* stream)
     HIP_OK(hipMemcpyAsync(h, c->counters.p, sizeof(int64_t) * kCounters,
                           hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
-    for (int k = 0; k < 5; ++k) out[k] = h[k];
+    for (int k = 0; k < 6; ++k) out[k] = h[k];
     return HERMITE_OK;
 }
 
@@ -858,6 +971,35 @@ int hermite_get_tuning(hermite_ctx* c, int precision, hermite_tuning* out)
     if (!c || !out) return fail(HERMITE_EINVAL, "null argument");
     CHECK(check_precision(precision));
     *out = c->tuning[precision];
+    return HERMITE_OK;
+}
+
+int hermite_set_mixed_policy(hermite_ctx* c, int precision, double near_factor,
+                             int64_t fp64_below)
+{
+    if (!c) return fail(HERMITE_EINVAL, "null context");
+    CHECK(check_precision(precision));
+    if (precision == HERMITE_FP64)
+        return fail(HERMITE_EINVAL, "the FP64 sweep has no mixed-precision policy");
+    if (!(near_factor >= 0.0) || std::isinf(near_factor))
+        return fail(HERMITE_EINVAL, "near-field radius factor must be finite and >= 0");
+    if (fp64_below < 0)
+        return fail(HERMITE_EINVAL, "fp64_below must be >= 0");
+    if (precision == HERMITE_MIXED_SP && fp64_below != 0)
+        return fail(HERMITE_EINVAL, "the paper-faithful mode has no FP64 systems (fp64_below = 0)");
+    drop_graphs(c);
+    c->near_factor[precision] = near_factor;
+    c->fp64_below[precision] = fp64_below;
+    return HERMITE_OK;
+}
+
+int hermite_get_mixed_policy(hermite_ctx* c, int precision, double* near_factor,
+                             int64_t* fp64_below)
+{
+    if (!c || !near_factor || !fp64_below) return fail(HERMITE_EINVAL, "null argument");
+    CHECK(check_precision(precision));
+    *near_factor = precision == HERMITE_FP64 ? 0.0 : c->near_factor[precision];
+    *fp64_below = precision == HERMITE_FP64 ? 0 : c->fp64_below[precision];
     return HERMITE_OK;
 }
 
@@ -994,7 +1136,7 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
     auto run_p = [&](int prec, const hermite_tuning& tu, int reps, double* us,
                      std::vector<double>* res) -> int {
         SweepArgs a;
-        CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, nullptr, n_act, eps2, tu, out,
+        CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, nullptr, n_act, eps2, prec, tu, out,
                             out + 3 * (size_t)n_act, out + 6 * (size_t)n_act, &a));
         a.counters = nullptr;
         CHECK(run_force(c, a, prec, tu, false, st));   // warm-up

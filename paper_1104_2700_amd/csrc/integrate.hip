@@ -1001,7 +1001,7 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     if (thread_reduce(sa.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
-            double s[7];
+            double s[kRows];
             reduce_partials(sa, na, p, s);
             const double a1[3] = {s[0], s[1], s[2]};
             const double j1[3] = {s[3], s[4], s[5]};
@@ -1011,7 +1011,7 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
         const int lane = threadIdx.x & 63;
         const int wpb = kWG / 64;
         for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
-            double s[7];
+            double s[kRows];
             reduce_partials_wave(sa, na, p, lane, s);
             if (lane == 0) {
                 const double a1[3] = {s[0], s[1], s[2]};
@@ -1019,6 +1019,37 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
                 correct_one(c, p, T, a1, j1, s[6], true);
             }
         }
+    }
+}
+
+// The block-step corrector of a refined mixed sweep: the mixed sums from
+// the compact outputs, or, for a flagged position, the FP64 refine
+// sweep's partials summed in chunk order.
+__global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, SweepArgs ra)
+{
+    const int na = *c.n_act_dev;
+    if (c.na_seen && blockIdx.x == 0 && threadIdx.x == 0) *c.na_seen = na;
+    const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
+    const int64_t st = c.n_act_max;
+    const int cnt = ra.plan->n_act;
+    for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
+        const int k = ra.ref_pos[p];
+        double a1[3], j1[3], pot1;
+        if (k >= 0) {
+            double s[kRows];
+            reduce_partials(ra, cnt, k, s);
+            a1[0] = s[0]; a1[1] = s[1]; a1[2] = s[2];
+            j1[0] = s[3]; j1[1] = s[4]; j1[2] = s[5];
+            pot1 = s[6];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                a1[d] = c.acc1[d * st + p];
+                j1[d] = c.jrk1[d * st + p];
+            }
+            pot1 = c.pot1[p];
+        }
+        correct_one(c, p, T, a1, j1, pot1, true);
     }
 }
 
@@ -1176,6 +1207,13 @@ hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipS
 {
     hipLaunchKernelGGL(correct_reduce_kernel, dim3(reduce_grid(c.n_act_max)), dim3(kWG), 0,
                        st, c, sa);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& ra, hipStream_t st)
+{
+    hipLaunchKernelGGL(correct_refine_kernel, dim3(reduce_grid(c.n_act_max)), dim3(kWG), 0, st,
+                       c, ra);
     return hipGetLastError();
 }
 

@@ -138,9 +138,9 @@ __host__ __device__ inline void plan_split(const SweepArgs& a, int32_t na, int64
     // tuning factor), and the most j-chunks a cluster can give (each chunk
     // at least one LDS tile, all partial sums in the buffer).
     const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
-    int64_t s_cap = (a.n_cmax + kTJ - 1) / kTJ;
+    int64_t s_cap = a.one_chunk ? 1 : (a.n_cmax + kTJ - 1) / kTJ;
     if (na > 0) {
-        const int64_t buf_cap = a.partial_cap / (7 * (int64_t)na);
+        const int64_t buf_cap = a.partial_cap / (kRows * (int64_t)na);
         if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
     }
     // Fewest lanes per particle that (a) still yields enough items and
@@ -321,51 +321,84 @@ __device__ inline int cluster_of(const SweepArgs& a, int p)
     return upper_bound_i64(a.offsets, a.n_clusters + 1, i) - 1;
 }
 
+// The sweep's error estimates travel as two FP32 numbers in the bits of
+// one double (row 7 of the partial sums): the sums over the lane's FP32
+// runs of |run sum|^2 for the acceleration (lo word) and the jerk (hi).
+__device__ __forceinline__ double pack_est(float ea, float ej)
+{
+    const uint64_t b = (uint64_t)__float_as_uint(ea) | ((uint64_t)__float_as_uint(ej) << 32);
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ void unpack_est(double d, float* ea, float* ej)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    *ea = __uint_as_float((uint32_t)b);
+    *ej = __uint_as_float((uint32_t)(b >> 32));
+}
+
 // Sum, in chunk order, of the partial results of active position p:
-// out = acc xyz, jerk xyz, pot.  One thread per particle.
-// Chunks are read kReduceBatch at a time from clamped addresses, so their
-// loads are in flight together; the sum is still taken in chunk order (a
-// chunk past the end adds +0.0, which leaves a sum that started at +0.0
-// unchanged bit for bit).
+// out = acc xyz, jerk xyz, pot, and (row 7) the packed error estimates.
+// One thread per particle.  Chunks are read kReduceBatch at a time from
+// clamped addresses, so their loads are in flight together; the sum is
+// still taken in chunk order (a chunk past the end adds +0.0, which leaves
+// a sum that started at +0.0 unchanged bit for bit).
 constexpr int kReduceBatch = 4;
 
-__device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[7])
+__device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[kRows])
 {
     const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) out[q] = 0.0;
+    for (int q = 0; q < kRows; ++q) out[q] = 0.0;
+    float ea = 0.0f, ej = 0.0f;
     for (int k = 0; k < ch; k += kReduceBatch) {
-        double v[kReduceBatch][7];
+        double v[kReduceBatch][kRows];
 #pragma unroll
         for (int u = 0; u < kReduceBatch; ++u) {
             const int kk = k + u < ch ? k + u : ch - 1;
 #pragma unroll
-            for (int q = 0; q < 7; ++q) v[u][q] = a.partial[((int64_t)kk * 7 + q) * na + p];
+            for (int q = 0; q < kRows; ++q)
+                v[u][q] = a.partial[((int64_t)kk * kRows + q) * na + p];
         }
 #pragma unroll
         for (int u = 0; u < kReduceBatch; ++u) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) out[q] += k + u < ch ? v[u][q] : 0.0;
+            for (int q = 0; q < kRows - 1; ++q) out[q] += k + u < ch ? v[u][q] : 0.0;
+            float xa, xj;
+            unpack_est(v[u][kRows - 1], &xa, &xj);
+            ea += k + u < ch ? xa : 0.0f;
+            ej += k + u < ch ? xj : 0.0f;
         }
     }
+    out[kRows - 1] = pack_est(ea, ej);
 }
 
 // The same sum by a whole wave (for many chunks): lane l adds chunks
 // l, l + 64, ... in order, then a fixed xor butterfly combines the lanes.
 // Every lane returns the total.  Deterministic for a given chunk count.
 __device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, int lane,
-                                            double out[7])
+                                            double out[kRows])
 {
     const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) out[q] = 0.0;
+    for (int q = 0; q < kRows; ++q) out[q] = 0.0;
+    float ea = 0.0f, ej = 0.0f;
     for (int k = lane; k < ch; k += 64) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) out[q] += a.partial[((int64_t)k * 7 + q) * na + p];
+        for (int q = 0; q < kRows - 1; ++q) out[q] += a.partial[((int64_t)k * kRows + q) * na + p];
+        float xa, xj;
+        unpack_est(a.partial[((int64_t)k * kRows + kRows - 1) * na + p], &xa, &xj);
+        ea += xa;
+        ej += xj;
     }
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
+    for (int q = 0; q < kRows - 1; ++q)
         for (int o = 1; o < 64; o <<= 1) out[q] += __shfl_xor(out[q], o);
+    for (int o = 1; o < 64; o <<= 1) {
+        ea += __shfl_xor(ea, o);
+        ej += __shfl_xor(ej, o);
+    }
+    out[kRows - 1] = pack_est(ea, ej);
 }
 
 // Position and velocity of particle i for the sweep: predicted on the fly
@@ -403,6 +436,163 @@ constexpr int kThreadReduceMinAct = 16384;
 __device__ __forceinline__ bool thread_reduce(int s_max, int na)
 {
     return s_max <= kWaveReduceChunks || na >= kThreadReduceMinAct;
+}
+
+// ------------------------------------------------------------------------
+// A-posteriori FP64 refinement of the mixed precisions.
+//
+// Each lane of a mixed sweep accumulates E = sum over its FP32 runs of
+// |run sum|^2 (acceleration and jerk separately).  With the near pairs in
+// FP64, a particle's remaining error is a random walk of per-term FP32
+// errors, and u32 sqrt(E) tracks its size: the ratio of the true error to
+// it stays below about 13 on the N = 65536 Plummer sample (CPU emulation
+// of the kernel's arithmetic).  A particle whose u32 sqrt(E) exceeds
+// kRefineRel times its acceleration or jerk magnitude could come near the
+// 1e-6 bar (a sum that almost cancels).  The reduce stage flags such
+// particles; its last workgroup lists them in active-list order and plans
+// a second sweep, in FP64, with the flagged particles as its active list
+// (j is streamed once per tile of them, as in any sweep); their refined
+// sums then replace the mixed ones.
+// ------------------------------------------------------------------------
+constexpr double kRefineRel = 4e-8;
+
+__device__ inline bool needs_refine(const SweepArgs& a, const double s[kRows])
+{
+    if (!a.refine) return false;
+    float ea, ej;
+    unpack_est(s[kRows - 1], &ea, &ej);
+    const double u32 = 0x1p-24;
+    const double A = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double J = sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+    return u32 * sqrt((double)ea) > kRefineRel * A || u32 * sqrt((double)ej) > kRefineRel * J;
+}
+
+// Exclusive scan of one value per thread over the workgroup (all kWG
+// threads call it); *total receives the sum.
+__device__ inline int32_t block_exscan(int32_t v, int32_t* total)
+{
+    __shared__ int32_t s_w[kWG / 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    int32_t off = x - v, tot = 0;
+    for (int w = 0; w < kWG / 64; ++w) {
+        off += w < wave ? s_w[w] : 0;
+        tot += s_w[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off;
+}
+
+// The flagging reduce handles the active positions in units: one round of
+// a workgroup, kWG positions (a thread each) or kWG / 64 (a wave each).
+// Every thread of the workgroup calls this once per round, with its flag
+// (only for a position it owns): the unit's flagged positions are written
+// compactly at the start of its own position range in ref_tmp and their
+// count to ref_ucnt[unit].  ref_pos of every owned position becomes -1.
+__device__ inline void flag_unit(const SweepArgs& a, int unit, int base, int p, bool owner,
+                                 bool flag)
+{
+    int32_t tot;
+    const int32_t off = block_exscan(owner && flag ? 1 : 0, &tot);
+    if (owner) {
+        a.ref_pos[p] = -1;
+        if (flag) a.ref_tmp[base + off] = p;
+    }
+    if (threadIdx.x == 0) a.ref_ucnt[unit] = tot;
+}
+
+// One workgroup, after the flagging reduce: the refine list from the
+// units' counts and compacted positions, in unit order (with clusters,
+// grouped by cluster: each cluster's run starts at the sum of the counts
+// before it, entries in any order within it), ref_pos of the flagged
+// positions set to their slots, and the plan of the refine sweep ra.
+// Returns the count.  Which slot a particle takes does not change its
+// refined sums: every slot is swept with the same split.
+__device__ inline int32_t build_refine_list(const SweepArgs& a, const SweepArgs& ra, int32_t na,
+                                            int unit_size)
+{
+    __shared__ int32_t s_run;
+    const int tid = threadIdx.x;
+    const int nu = (na + unit_size - 1) / unit_size;
+    // units' counts -> their first slot (exclusive scan, kWG units at a time)
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    for (int u0 = 0; u0 < nu; u0 += kWG) {
+        const int u = u0 + tid;
+        const int32_t v = u < nu ? a.ref_ucnt[u] : 0;
+        int32_t tot;
+        const int32_t off = block_exscan(v, &tot);
+        if (u < nu) a.ref_ucnt[u] = s_run + off;
+        __syncthreads();
+        if (tid == 0) s_run += tot;
+        __syncthreads();
+    }
+    const int32_t cnt = s_run;
+    const int C = a.n_clusters;
+    if (C == 1) {
+        for (int u = tid; u < nu; u += kWG) {
+            const int32_t k0 = a.ref_ucnt[u];
+            const int32_t k1 = u + 1 < nu ? a.ref_ucnt[u + 1] : cnt;
+            for (int32_t k = k0; k < k1; ++k) {
+                const int p = a.ref_tmp[u * unit_size + (k - k0)];
+                a.ref_idx[k] = a.idx ? a.idx[p] : p;
+                a.ref_p[k] = p;
+                a.ref_pos[p] = k;
+            }
+        }
+    } else {
+        // per-cluster counts, their exclusive scan (the run starts of the
+        // refine sweep) and placement through per-cluster cursors
+        for (int c = tid; c < C; c += kWG) a.ref_ccnt[c] = 0;
+        __syncthreads();
+        for (int u = tid; u < nu; u += kWG) {
+            const int32_t k0 = a.ref_ucnt[u];
+            const int32_t k1 = u + 1 < nu ? a.ref_ucnt[u + 1] : cnt;
+            for (int32_t k = k0; k < k1; ++k)
+                atomicAdd(&a.ref_ccnt[cluster_of(a, a.ref_tmp[u * unit_size + (k - k0)])], 1);
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) s_run = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < C; c0 += kWG) {
+            const int c = c0 + tid;
+            const int32_t v = c < C ? a.ref_ccnt[c] : 0;
+            int32_t tot;
+            const int32_t off = block_exscan(v, &tot);
+            if (c < C) {
+                ra.act_start[c] = s_run + off;
+                a.ref_ccnt[c] = s_run + off;
+            }
+            __syncthreads();
+            if (tid == 0) s_run += tot;
+            __syncthreads();
+        }
+        __threadfence_block();
+        for (int u = tid; u < nu; u += kWG) {
+            const int32_t k0 = a.ref_ucnt[u];
+            const int32_t k1 = u + 1 < nu ? a.ref_ucnt[u + 1] : cnt;
+            for (int32_t k = k0; k < k1; ++k) {
+                const int p = a.ref_tmp[u * unit_size + (k - k0)];
+                const int32_t slot = atomicAdd(&a.ref_ccnt[cluster_of(a, p)], 1);
+                a.ref_idx[slot] = a.idx ? a.idx[p] : p;
+                a.ref_p[slot] = p;
+                a.ref_pos[p] = slot;
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    plan_body(ra, cnt);
+    return cnt;
 }
 
 }  // namespace hm

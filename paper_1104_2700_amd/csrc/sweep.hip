@@ -48,6 +48,10 @@ namespace {
 
 constexpr int kMixedK = 16;   // FP32 run length before an FP64 flush
 
+#ifndef HM_MIXED_NR
+#define HM_MIXED_NR 0
+#endif
+
 __device__ __forceinline__ double rsqrt_f64(double s)
 {
     // y0 from the hardware; with e = 1 - s y0^2,
@@ -71,11 +75,13 @@ struct I64 {   // i-particle in FP64
     double x, y, z, vx, vy, vz;
 };
 
-struct SumD {  // FP64 sums: acc, jerk, sum of m/r
+struct SumD {  // FP64 sums: acc, jerk, sum of m/r; FP32 error estimates
     double ax, ay, az, jx, jy, jz, pp;
+    float ea, ej;  // sums over FP32 runs of |run sum|^2 (acc, jerk)
     __device__ __forceinline__ void zero()
     {
         ax = ay = az = jx = jy = jz = pp = 0.0;
+        ea = ej = 0.0f;
     }
     __device__ __forceinline__ void add(const SumD& o)
     {
@@ -103,6 +109,13 @@ struct TwoF {  // one two-float running sum
         hi = s;
         lo += err;
     }
+    // adds an FP64 value as its two FP32 words
+    __device__ __forceinline__ void add_d(double d)
+    {
+        const float h = (float)d;
+        add(h);
+        lo += (float)(d - (double)h);
+    }
     __device__ __forceinline__ double value() const
     {
         return (double)hi + (double)lo;
@@ -111,9 +124,11 @@ struct TwoF {  // one two-float running sum
 
 struct Sum2F {
     TwoF ax, ay, az, jx, jy, jz, pp;
+    float ea, ej;  // as in SumD
     __device__ __forceinline__ void zero()
     {
         ax = ay = az = jx = jy = jz = pp = TwoF{0.0f, 0.0f};
+        ea = ej = 0.0f;
     }
 };
 
@@ -156,19 +171,73 @@ __device__ __forceinline__ void pot_f64(const I64& I, double eps2, double xj,
     S.pp = fma(mj, ri, S.pp);
 }
 
-// One mixed-precision pair term: FP64 differences, FP32 pair arithmetic.
-template <bool MASK>
-__device__ __forceinline__ void pair_mixed(const I64& I, float eps2f, double xj,
-                                           double yj, double zj, double vxj,
-                                           double vyj, double vzj, float mj,
-                                           bool self, SumF& S)
+
+// ---- mixed precision: FP32 pair arithmetic with an FP64 near field ------
+//
+// With FP32 pair arithmetic every pair term carries a relative error of a
+// few u32, and a particle's error is their random walk weighted by the
+// terms' magnitudes, i.e. dominated by its nearest neighbours, whose terms
+// are the largest.  Pairs closer than the near-field radius (r^2 <= near2:
+// a few mean interparticle spacings, set per cluster from its size) are
+// therefore evaluated in FP64 instead, in a divergent branch that the wave
+// takes only for the few j that are near one of its particles.  The self
+// pair (r^2 = eps^2 exactly) always takes that branch, where an index
+// compare drops it: no separate masked tile loop is needed.
+
+__device__ __forceinline__ float rsq_f32(float s)
 {
-    const float dx = (float)(xj - I.x), dy = (float)(yj - I.y), dz = (float)(zj - I.z);
-    const float dvx = (float)(vxj - I.vx), dvy = (float)(vyj - I.vy),
-                dvz = (float)(vzj - I.vz);
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    if (MASK) ri = self ? 0.0f : ri;
+    float y = __builtin_amdgcn_rsqf(s);
+#if HM_MIXED_NR
+    // one Newton step, y (1 + e/2) with e = 1 - s y^2 (Section 3.2)
+    const float h = s * y;
+    const float e = fmaf(-h, y, 1.0f);
+    y = fmaf(y * 0.5f, e, y);
+#endif
+    return y;
+}
+
+// FP64 terms of one near pair from FP64 differences: acc xyz, jerk xyz and
+// m/r (the self pair gives zeros).
+__device__ __forceinline__ void near_terms(double dx, double dy, double dz, double dvx,
+                                           double dvy, double dvz, double mj, double eps2,
+                                           bool self, double o[7])
+{
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+    const double y = rsqrt_f64(r2);
+    const double ri = self ? 0.0 : y;
+    const double mr = mj * ri;
+    const double ri2 = ri * ri;
+    const double mr3 = mr * ri2;
+    const double rv = fma(dx, dvx, fma(dy, dvy, dz * dvz));
+    const double b3 = (rv * ri2) * 3.0;
+    o[0] = mr3 * dx;
+    o[1] = mr3 * dy;
+    o[2] = mr3 * dz;
+    o[3] = mr3 * fma(-b3, dx, dvx);
+    o[4] = mr3 * fma(-b3, dy, dvy);
+    o[5] = mr3 * fma(-b3, dz, dvz);
+    o[6] = mr;
+}
+
+__device__ __forceinline__ void add_near(SumD& S, const double o[7])
+{
+    S.ax += o[0]; S.ay += o[1]; S.az += o[2];
+    S.jx += o[3]; S.jy += o[4]; S.jz += o[5];
+    S.pp += o[6];
+}
+
+__device__ __forceinline__ void add_near(Sum2F& S, const double o[7])
+{
+    S.ax.add_d(o[0]); S.ay.add_d(o[1]); S.az.add_d(o[2]);
+    S.jx.add_d(o[3]); S.jy.add_d(o[4]); S.jz.add_d(o[5]);
+    S.pp.add_d(o[6]);
+}
+
+// The FP32 part of a mixed pair term, shared by every mixed form.
+__device__ __forceinline__ void far_terms(float dx, float dy, float dz, float dvx, float dvy,
+                                          float dvz, float r2, float ri, float mj, SumF& S)
+{
+    (void)r2;
     const float mr = mj * ri;
     const float ri2 = ri * ri;
     const float mr3 = mr * ri2;
@@ -183,12 +252,68 @@ __device__ __forceinline__ void pair_mixed(const I64& I, float eps2f, double xj,
     S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
 }
 
+// Near-field test and parameters of one work item.
+struct NearF {
+    float near2f;   // FP32 threshold on r^2 + eps^2 (>= eps^2 in FP32)
+    double eps2;    // FP64 softening of the near terms
+};
+
+// Mixed pair terms.  The FP32 part runs branch-free for every pair, with
+// the near pairs' 1/r masked to zero; it returns whether the pair is far
+// (not near; a NaN distance counts as far and poisons the FP32 sums).  The
+// caller evaluates the (rare) near pairs in FP64 later.
+__device__ __forceinline__ bool far_pair(float dx, float dy, float dz, float dvx, float dvy,
+                                         float dvz, float eps2f, float near2f, float mj,
+                                         SumF& S)
+{
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+    const bool far = !(r2 <= near2f);
+    const float ri = far ? rsq_f32(r2) : 0.0f;
+    far_terms(dx, dy, dz, dvx, dvy, dvz, r2, ri, mj, S);
+    return far;
+}
+
+// The near test of a pair, repeated bit for bit after the FP32 pass.
+__device__ __forceinline__ bool near_test(float dx, float dy, float dz, float eps2f,
+                                          float near2f)
+{
+    return fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f))) <= near2f;
+}
+
+// Cast form: FP64 differences rounded to FP32.
+__device__ __forceinline__ bool pair_mixed(const I64& I, float eps2f, float near2f, double xj,
+                                           double yj, double zj, double vxj, double vyj,
+                                           double vzj, float mj, SumF& S)
+{
+    return far_pair((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z),
+                    (float)(vxj - I.vx), (float)(vyj - I.vy), (float)(vzj - I.vz), eps2f,
+                    near2f, mj, S);
+}
+
+__device__ __forceinline__ bool near_mixed_test(const I64& I, float eps2f, float near2f,
+                                                double xj, double yj, double zj)
+{
+    return near_test((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z), eps2f, near2f);
+}
+
+template <typename RUN>
+__device__ __forceinline__ void near_mixed(const I64& I, const NearF& nf, double xj, double yj,
+                                           double zj, double vxj, double vyj, double vzj,
+                                           double mj, bool self, RUN& R)
+{
+    double o[7];
+    near_terms(xj - I.x, yj - I.y, zj - I.z, vxj - I.vx, vyj - I.vy, vzj - I.vz, mj, nf.eps2,
+               self, o);
+    add_near(R, o);
+}
+
 // Split form of the mixed pair term: every FP64 coordinate c is held as
 // hi = fl32(c), lo = fl32(c - hi), and the difference is formed in FP32 as
-// (hi_j - hi_i) + (lo_j - lo_i).  For a close pair the hi difference is
-// exact (Sterbenz), so the result carries the same FP32 rounding of the
-// FP64 difference as the cast form, at three FP32 operations instead of
-// an FP64 subtraction and a conversion.
+// (hi_j - hi_i) + (lo_j - lo_i).  When both coordinates share a sign and
+// lie within a factor of two the hi difference is exact (Sterbenz) and the
+// result carries the one FP32 rounding of the cast form; otherwise (far
+// pairs) it may round twice.  Near pairs are rebuilt in FP64 from the
+// words (hi + lo holds c to 2^-48 relative).
 struct I32S {  // i-particle, split coordinates
     float xh, xl, yh, yl, zh, zl, vxh, vxl, vyh, vyl, vzh, vzl;
 };
@@ -199,62 +324,70 @@ __device__ __forceinline__ void split(double c, float& h, float& l)
     l = (float)(c - (double)h);
 }
 
-template <bool MASK>
-__device__ __forceinline__ void pair_split(const I32S& I, float eps2f, const float* J,
-                                           float mj, bool self, SumF& S)
+__device__ __forceinline__ double join_diff(float jh, float jl, float ih, float il)
 {
-    const float dx = (J[0] - I.xh) + (J[1] - I.xl);
-    const float dy = (J[2] - I.yh) + (J[3] - I.yl);
-    const float dz = (J[4] - I.zh) + (J[5] - I.zl);
-    const float dvx = (J[6] - I.vxh) + (J[7] - I.vxl);
-    const float dvy = (J[8] - I.vyh) + (J[9] - I.vyl);
-    const float dvz = (J[10] - I.vzh) + (J[11] - I.vzl);
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    if (MASK) ri = self ? 0.0f : ri;
-    const float mr = mj * ri;
-    const float ri2 = ri * ri;
-    const float mr3 = mr * ri2;
-    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-    const float b3 = (rv * ri2) * 3.0f;
-    S.pp += mr;
-    S.ax = fmaf(mr3, dx, S.ax);
-    S.ay = fmaf(mr3, dy, S.ay);
-    S.az = fmaf(mr3, dz, S.az);
-    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
-    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
-    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+    return ((double)jh - (double)ih) + ((double)jl - (double)il);
+}
+
+__device__ __forceinline__ bool pair_split(const I32S& I, float eps2f, float near2f,
+                                           const float* J, float mj, SumF& S)
+{
+    return far_pair((J[0] - I.xh) + (J[1] - I.xl), (J[2] - I.yh) + (J[3] - I.yl),
+                    (J[4] - I.zh) + (J[5] - I.zl), (J[6] - I.vxh) + (J[7] - I.vxl),
+                    (J[8] - I.vyh) + (J[9] - I.vyl), (J[10] - I.vzh) + (J[11] - I.vzl), eps2f,
+                    near2f, mj, S);
+}
+
+__device__ __forceinline__ bool near_split_test(const I32S& I, float eps2f, float near2f,
+                                                const float* J)
+{
+    return near_test((J[0] - I.xh) + (J[1] - I.xl), (J[2] - I.yh) + (J[3] - I.yl),
+                     (J[4] - I.zh) + (J[5] - I.zl), eps2f, near2f);
+}
+
+template <typename RUN>
+__device__ __forceinline__ void near_split(const I32S& I, const NearF& nf, const float* J,
+                                           double mj, bool self, RUN& R)
+{
+    double o[7];
+    near_terms(join_diff(J[0], J[1], I.xh, I.xl), join_diff(J[2], J[3], I.yh, I.yl),
+               join_diff(J[4], J[5], I.zh, I.zl), join_diff(J[6], J[7], I.vxh, I.vxl),
+               join_diff(J[8], J[9], I.vyh, I.vyl), join_diff(J[10], J[11], I.vzh, I.vzl), mj,
+               nf.eps2, self, o);
+    add_near(R, o);
 }
 
 // Paper-faithful mixed term (Section 3.2 as printed): velocities held in
 // FP32 and their difference taken in FP32; everything else as pair_mixed.
+// Its near field (radius 0 by default) holds the self pair and coincident
+// particles only.
 struct I64SP {  // i-particle: FP64 position, FP32 velocity
     double x, y, z;
     float vx, vy, vz;
 };
 
-template <bool MASK>
-__device__ __forceinline__ void pair_sp(const I64SP& I, float eps2f, double xj, double yj,
-                                        double zj, float vxj, float vyj, float vzj, float mj,
-                                        bool self, SumF& S)
+__device__ __forceinline__ bool pair_sp(const I64SP& I, float eps2f, float near2f, double xj,
+                                        double yj, double zj, float vxj, float vyj, float vzj,
+                                        float mj, SumF& S)
 {
-    const float dx = (float)(xj - I.x), dy = (float)(yj - I.y), dz = (float)(zj - I.z);
-    const float dvx = vxj - I.vx, dvy = vyj - I.vy, dvz = vzj - I.vz;
-    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    if (MASK) ri = self ? 0.0f : ri;
-    const float mr = mj * ri;
-    const float ri2 = ri * ri;
-    const float mr3 = mr * ri2;
-    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-    const float b3 = (rv * ri2) * 3.0f;
-    S.pp += mr;
-    S.ax = fmaf(mr3, dx, S.ax);
-    S.ay = fmaf(mr3, dy, S.ay);
-    S.az = fmaf(mr3, dz, S.az);
-    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
-    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
-    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+    return far_pair((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z), vxj - I.vx,
+                    vyj - I.vy, vzj - I.vz, eps2f, near2f, mj, S);
+}
+
+__device__ __forceinline__ bool near_sp_test(const I64SP& I, float eps2f, float near2f,
+                                             double xj, double yj, double zj)
+{
+    return near_test((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z), eps2f, near2f);
+}
+
+__device__ __forceinline__ void near_sp(const I64SP& I, const NearF& nf, double xj, double yj,
+                                        double zj, float vxj, float vyj, float vzj, double mj,
+                                        bool self, SumD& R)
+{
+    double o[7];
+    near_terms(xj - I.x, yj - I.y, zj - I.z, (double)vxj - (double)I.vx,
+               (double)vyj - (double)I.vy, (double)vzj - (double)I.vz, mj, nf.eps2, self, o);
+    add_near(R, o);
 }
 
 // Flush of the paper-faithful mode: acceleration and potential runs go to
@@ -266,8 +399,17 @@ __device__ __forceinline__ void flush_keep_jerk(SumF& f, SumD& d)
     f.ax = f.ay = f.az = f.pp = 0.0f;
 }
 
+// Error estimate of the mixed paths: the squares of each FP32 run sum.
+template <typename RUN>
+__device__ __forceinline__ void add_estimate(const SumF& f, RUN& d)
+{
+    d.ea = fmaf(f.ax, f.ax, fmaf(f.ay, f.ay, fmaf(f.az, f.az, d.ea)));
+    d.ej = fmaf(f.jx, f.jx, fmaf(f.jy, f.jy, fmaf(f.jz, f.jz, d.ej)));
+}
+
 __device__ __forceinline__ void flush(SumF& f, SumD& d)
 {
+    add_estimate(f, d);
     d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
     d.jx += (double)f.jx; d.jy += (double)f.jy; d.jz += (double)f.jz;
     d.pp += (double)f.pp;
@@ -276,30 +418,63 @@ __device__ __forceinline__ void flush(SumF& f, SumD& d)
 
 __device__ __forceinline__ void flush(SumF& f, Sum2F& d)
 {
+    add_estimate(f, d);
     d.ax.add(f.ax); d.ay.add(f.ay); d.az.add(f.az);
     d.jx.add(f.jx); d.jy.add(f.jy); d.jz.add(f.jz);
     d.pp.add(f.pp);
     f.zero();
 }
 
-// LDS tile of j-particles (SoA).  Masses are FP32 in the mixed paths.
+// LDS tile of j-particles (SoA), FP64 path.
 template <typename MT>
 struct Tile {
     double x[kTJ], y[kTJ], z[kTJ], vx[kTJ], vy[kTJ], vz[kTJ];
     MT m[kTJ];
 };
 
+// The mixed tiles have kTJPad slots: those past the staged particles hold
+// zero-mass particles at 1e30 (finite in FP32, r^2 overflows to +inf, so
+// 1/r = 0, the pair adds exactly zero and is never near).  A lane may read
+// up to L - 1 slots past a ragged tile's end.
+constexpr int kTJPad = kTJ + 64;
+constexpr double kFarAway = 1e30;
+
+// Mixed (cast form): FP64 coordinates; the mass as FP32 hi and lo words
+// (hi for the FP32 terms, hi + lo for the FP64 near terms).
+struct TileM {
+    double x[kTJPad], y[kTJPad], z[kTJPad], vx[kTJPad], vy[kTJPad], vz[kTJPad];
+    float m[kTJPad], mlo[kTJPad];
+    __device__ void pad(int k)
+    {
+        x[k] = y[k] = z[k] = kFarAway;
+        vx[k] = vy[k] = vz[k] = 0.0;
+        m[k] = mlo[k] = 0.0f;
+    }
+};
+
 // LDS tile of j-particles with split coordinates: c[k][j] for the twelve
-// hi/lo words (x, y, z, vx, vy, vz), and the FP32 mass.
+// hi/lo words (x, y, z, vx, vy, vz), and the mass words.
 struct TileS {
-    float c[12][kTJ];
-    float m[kTJ];
+    float c[12][kTJPad];
+    float m[kTJPad], mlo[kTJPad];
+    __device__ void pad(int k)
+    {
+#pragma unroll
+        for (int w = 0; w < 12; ++w) c[w][k] = (w < 6 && (w & 1) == 0) ? (float)kFarAway : 0.0f;
+        m[k] = mlo[k] = 0.0f;
+    }
 };
 
 // LDS tile for the paper-faithful mode: FP64 positions, FP32 velocities.
 struct TileSP {
-    double x[kTJ], y[kTJ], z[kTJ];
-    float vx[kTJ], vy[kTJ], vz[kTJ], m[kTJ];
+    double x[kTJPad], y[kTJPad], z[kTJPad];
+    float vx[kTJPad], vy[kTJPad], vz[kTJPad], m[kTJPad], mlo[kTJPad];
+    __device__ void pad(int k)
+    {
+        x[k] = y[k] = z[k] = kFarAway;
+        vx[k] = vy[k] = vz[k] = 0.0f;
+        m[k] = mlo[k] = 0.0f;
+    }
 };
 
 // ---- tile loops ---------------------------------------------------------
@@ -344,81 +519,163 @@ __device__ __forceinline__ void tile_pot(const Tile<double>& T, int cnt, int sub
     S.pp += t.pp;
 }
 
-template <bool MASK, int IPL, typename RUN>
-__device__ __forceinline__ void tile_mixed(const Tile<float>& T, int cnt, int sub,
-                                           int L, int64_t tb, const int (&ii)[IPL],
-                                           const I64 (&I)[IPL], float eps2f,
-                                           SumF (&f)[IPL], RUN (&S)[IPL])
+
+// Mixed tile loops.  Each lane takes runs of kMixedK of its j (every L-th
+// j of the tile).  A run's pair terms are summed in FP32 with no branch and
+// no per-lane guard: slots past the tile's end hold zero-mass particles far
+// away (see pad_tile), so every lane runs the same trip count, and near
+// pairs are masked to zero.  The wave notes in one scalar word which of
+// the run's j met a near pair in some lane; after the run those j are
+// visited again (rare), the FP32 near test is repeated bit for bit and the
+// near pairs are evaluated in FP64 into the running sums.  Then the FP32
+// run sums are flushed.
+// bit if some lane's ballot bit is clear, else 0.  Scalar instructions only
+// (written out because the compiler otherwise moves the wave-uniform
+// condition through a vector register and back, two vector instructions
+// per j).
+__device__ __forceinline__ uint32_t run_hit_bit(uint64_t far_ballot, uint32_t bit)
 {
-    constexpr int kUnroll = IPL == 1 ? 4 : 2;
+    uint32_t t;
+    asm("s_cmp_lg_u64 %1, -1\n\ts_cselect_b32 %0, %2, 0"
+        : "=s"(t)
+        : "s"(far_ballot), "s"(bit)
+        : "scc");
+    return t;
+}
+
+template <typename FAR, typename NEARFN, typename FLUSH>
+__device__ __forceinline__ void mixed_runs(int cnt, int sub, int L, FAR far, NEARFN near_fn,
+                                           FLUSH flush_fn)
+{
     const int step = kMixedK * L;
     for (int jb = 0; jb < cnt; jb += step) {
         const int je = (jb + step < cnt) ? jb + step : cnt;
-#pragma unroll kUnroll
-        for (int jj = jb + sub; jj < je; jj += L) {
-            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
-            const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
-            const float mj = T.m[jj];
+        const int nk = (je - jb + L - 1) / L;   // j per lane in this run (uniform)
+        uint32_t hit = 0;
+        // every lane of the wave is active here: a lane that met a near pair
+        // at its k-th j clears its bit of that j's ballot.  (The ballot is a
+        // convergent operation, which rules out unrolling a loop of unknown
+        // trip count: full runs take the constant-trip form.)
+        if (nk == kMixedK) {
 #pragma unroll
-            for (int q = 0; q < IPL; ++q) {
-                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
-                pair_mixed<MASK>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, mj, self, f[q]);
-            }
+            for (int k = 0; k < kMixedK; ++k)
+                hit |= run_hit_bit(__builtin_amdgcn_ballot_w64(far(jb + sub + k * L)), 1u << k);
+        } else {
+            for (int k = 0; k < nk; ++k)
+                hit |= run_hit_bit(__builtin_amdgcn_ballot_w64(far(jb + sub + k * L)), 1u << k);
         }
-#pragma unroll
-        for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+        flush_fn();
+        while (__builtin_expect(hit != 0, 0)) {
+            const int k = __builtin_ctz(hit);
+            hit &= hit - 1;
+            near_fn(jb + sub + k * L);
+        }
     }
 }
 
-template <bool MASK, int IPL, typename RUN>
-__device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int L,
-                                           int64_t tb, const int (&ii)[IPL],
-                                           const I32S (&I)[IPL], float eps2f,
-                                           SumF (&f)[IPL], RUN (&S)[IPL])
+template <int IPL, typename RUN>
+__device__ __forceinline__ void tile_mixed(const TileM& T, int cnt, int sub, int L, int tb,
+                                           const int (&ii)[IPL], const I64 (&I)[IPL],
+                                           float eps2f, const NearF& nf, SumF (&f)[IPL],
+                                           RUN (&S)[IPL])
 {
-    constexpr int kUnroll = IPL == 1 ? 4 : 2;
-    const int step = kMixedK * L;
-    for (int jb = 0; jb < cnt; jb += step) {
-        const int je = (jb + step < cnt) ? jb + step : cnt;
-#pragma unroll kUnroll
-        for (int jj = jb + sub; jj < je; jj += L) {
+    mixed_runs(
+        cnt, sub, L,
+        [&](int jj) {
+            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+            const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
+            const float mj = T.m[jj];
+            bool fr = true;
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+                fr &= pair_mixed(I[q], eps2f, nf.near2f, xj, yj, zj, vxj, vyj, vzj, mj, f[q]);
+            return fr;
+        },
+        [&](int jj) {
+            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+            const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
+            const double mj = (double)T.m[jj] + (double)T.mlo[jj];
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                if (near_mixed_test(I[q], eps2f, nf.near2f, xj, yj, zj))
+                    near_mixed(I[q], nf, xj, yj, zj, vxj, vyj, vzj, mj, tb + jj == ii[q], S[q]);
+                __builtin_amdgcn_sched_barrier(0);   // one particle's FP64 pair at a time
+            }
+        },
+        [&]() {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+        });
+}
+
+template <int IPL, typename RUN>
+__device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int L, int tb,
+                                           const int (&ii)[IPL], const I32S (&I)[IPL],
+                                           float eps2f, const NearF& nf, SumF (&f)[IPL],
+                                           RUN (&S)[IPL])
+{
+    mixed_runs(
+        cnt, sub, L,
+        [&](int jj) {
             float J[12];
 #pragma unroll
             for (int w = 0; w < 12; ++w) J[w] = T.c[w][jj];
             const float mj = T.m[jj];
+            bool fr = true;
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) fr &= pair_split(I[q], eps2f, nf.near2f, J, mj, f[q]);
+            return fr;
+        },
+        [&](int jj) {
+            float J[12];
+#pragma unroll
+            for (int w = 0; w < 12; ++w) J[w] = T.c[w][jj];
+            const double mj = (double)T.m[jj] + (double)T.mlo[jj];
 #pragma unroll
             for (int q = 0; q < IPL; ++q) {
-                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
-                pair_split<MASK>(I[q], eps2f, J, mj, self, f[q]);
+                if (near_split_test(I[q], eps2f, nf.near2f, J))
+                    near_split(I[q], nf, J, mj, tb + jj == ii[q], S[q]);
+                __builtin_amdgcn_sched_barrier(0);   // one particle's FP64 pair at a time
             }
-        }
+        },
+        [&]() {
 #pragma unroll
-        for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
-    }
+            for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+        });
 }
 
-template <bool MASK, int IPL>
-__device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L, int64_t tb,
+template <int IPL>
+__device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L, int tb,
                                         const int (&ii)[IPL], const I64SP (&I)[IPL],
-                                        float eps2f, SumF (&f)[IPL], SumD (&S)[IPL])
+                                        float eps2f, const NearF& nf, SumF (&f)[IPL],
+                                        SumD (&S)[IPL])
 {
-    constexpr int kUnroll = IPL == 1 ? 4 : 2;
-    const int step = kMixedK * L;
-    for (int jb = 0; jb < cnt; jb += step) {
-        const int je = (jb + step < cnt) ? jb + step : cnt;
-#pragma unroll kUnroll
-        for (int jj = jb + sub; jj < je; jj += L) {
+    mixed_runs(
+        cnt, sub, L,
+        [&](int jj) {
             const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
             const float vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj], mj = T.m[jj];
+            bool fr = true;
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+                fr &= pair_sp(I[q], eps2f, nf.near2f, xj, yj, zj, vxj, vyj, vzj, mj, f[q]);
+            return fr;
+        },
+        [&](int jj) {
+            const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
+            const double mj = (double)T.m[jj] + (double)T.mlo[jj];
 #pragma unroll
             for (int q = 0; q < IPL; ++q) {
-                const bool self = MASK && (tb + jj == (int64_t)ii[q]);
-                pair_sp<MASK>(I[q], eps2f, xj, yj, zj, vxj, vyj, vzj, mj, self, f[q]);
+                if (near_sp_test(I[q], eps2f, nf.near2f, xj, yj, zj))
+                    near_sp(I[q], nf, xj, yj, zj, T.vx[jj], T.vy[jj], T.vz[jj], mj,
+                            tb + jj == ii[q], S[q]);
+                __builtin_amdgcn_sched_barrier(0);   // one particle's FP64 pair at a time
             }
-        }
+        },
+        [&]() {
 #pragma unroll
-        for (int q = 0; q < IPL; ++q) flush_keep_jerk(f[q], S[q]);
-    }
+            for (int q = 0; q < IPL; ++q) flush_keep_jerk(f[q], S[q]);
+        });
 }
 
 __device__ __forceinline__ double shfl_sum(double v, int L)
@@ -427,15 +684,22 @@ __device__ __forceinline__ double shfl_sum(double v, int L)
     return v;
 }
 
-// Final per-lane values: acc xyz, jerk xyz, pot (-sum m/r).
-__device__ __forceinline__ void finalize(const SumD& S, double out[7])
+__device__ __forceinline__ float shfl_sum_f(float v, int L)
+{
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Final per-lane values: acc xyz, jerk xyz, pot (-sum m/r); the error
+// estimates are combined separately (they are FP32).
+__device__ __forceinline__ void finalize(const SumD& S, double out[kRows])
 {
     out[0] = S.ax; out[1] = S.ay; out[2] = S.az;
     out[3] = S.jx; out[4] = S.jy; out[5] = S.jz;
     out[6] = -S.pp;
 }
 
-__device__ __forceinline__ void finalize(const Sum2F& S, double out[7])
+__device__ __forceinline__ void finalize(const Sum2F& S, double out[kRows])
 {
     out[0] = S.ax.value(); out[1] = S.ay.value(); out[2] = S.az.value();
     out[3] = S.jx.value(); out[4] = S.jy.value(); out[5] = S.jz.value();
@@ -461,9 +725,17 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
     using MT = typename std::conditional<PREC == 0, double, float>::type;
     using RUN = typename std::conditional<PREC == 2, Sum2F, SumD>::type;
     using TT = typename std::conditional<
-        SPLIT, TileS, typename std::conditional<PREC == 3, TileSP, Tile<MT>>::type>::type;
+        SPLIT, TileS,
+        typename std::conditional<
+            PREC == 3, TileSP,
+            typename std::conditional<PREC == 0, Tile<MT>, TileM>::type>::type>::type;
+    constexpr bool kMixed = !POT_ONLY && PREC != 0;
     __shared__ TT T;
     __shared__ int32_t s_ioff[kLdsClusters + 1];
+    if constexpr (kMixed) {
+        // the slots past a full tile are padding for the whole launch
+        for (int k = kTJ + (int)threadIdx.x; k < kTJPad; k += kWG) T.pad(k);
+    }
 
     // item offsets of the clusters in LDS when they fit (the item -> cluster
     // search then costs no global round trips)
@@ -549,6 +821,24 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
         const int64_t j1 = (j0 + jc < ce) ? j0 + jc : ce;
         const double eps2 = a.eps2_c ? a.eps2_c[c] : a.eps2;
         const float eps2f = (float)eps2;
+        // mixed near field: pairs with |r| < near_factor * N_c^(-1/3) (and
+        // the self pair) are summed in FP64
+        NearF nf;
+        nf.eps2 = eps2;
+        {
+            double r2n = eps2;
+            if (a.near_factor > 0.0) {
+                const double rn = a.near_factor / cbrt((double)(ce - cb));
+                r2n = fma(rn, rn, eps2);
+            }
+            nf.near2f = (float)r2n;    // >= fl32(eps2): the self pair is always near
+        }
+        // a mixed sweep of an ensemble runs as two launches: this kernel
+        // takes the items of one kind of system only (see SweepArgs::kind)
+        if (a.kind != 0 && ((ce - cb) < a.fp64_below) != (a.kind == 2)) {
+            item += (int)gridDim.x;
+            continue;
+        }
 
         bool valid[IPL];
         int pp[IPL], ii[IPL];
@@ -607,7 +897,9 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                             split(r[d], T.c[2 * d][tid], T.c[2 * d + 1][tid]);
                             split(w[d], T.c[6 + 2 * d][tid], T.c[7 + 2 * d][tid]);
                         }
-                        T.m[tid] = (float)a.m[jg];
+                        const double mj = a.m[jg];
+                        T.m[tid] = (float)mj;
+                        T.mlo[tid] = (float)(mj - (double)(float)mj);
                     } else {
                         T.x[tid] = r[0];
                         T.y[tid] = r[1];
@@ -615,55 +907,71 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
                         T.vx[tid] = w[0];   // rounded to FP32 in the paper-faithful mode
                         T.vy[tid] = w[1];
                         T.vz[tid] = w[2];
-                        T.m[tid] = (MT)a.m[jg];
+                        const double mj = a.m[jg];
+                        T.m[tid] = (MT)mj;
+                        if constexpr (PREC != 0) T.mlo[tid] = (float)(mj - (double)(MT)mj);
                     }
                 }
+            } else if constexpr (kMixed) {
+                T.pad(tid);   // a ragged tile: the rest of it is padding
             }
+
             __syncthreads();
-            bool mine = false;
+            if constexpr (POT_ONLY || PREC == 0) {
+                // FP64: the self pair is masked by an index compare, only in
+                // tiles that hold one of the wave's particles
+                bool mine = false;
 #pragma unroll
-            for (int q = 0; q < IPL; ++q)
-                mine = mine || ((int64_t)ii[q] >= tb && (int64_t)ii[q] < tb + cnt);
-            const bool need_mask = __any(mine);
-            if constexpr (POT_ONLY) {
-                if (need_mask) tile_pot<true>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
-                else           tile_pot<false>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
-            } else if constexpr (PREC == 0) {
-                if (need_mask) tile_f64<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
-                else           tile_f64<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+                for (int q = 0; q < IPL; ++q)
+                    mine = mine || ((int64_t)ii[q] >= tb && (int64_t)ii[q] < tb + cnt);
+                const bool need_mask = __any(mine);
+                if constexpr (POT_ONLY) {
+                    if (need_mask) tile_pot<true>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
+                    else           tile_pot<false>(T, cnt, sub, L, tb, ii[0], I[0], eps2, S[0]);
+                } else {
+                    if (need_mask) tile_f64<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+                    else           tile_f64<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
+                }
             } else if constexpr (SPLIT) {
-                if (need_mask) tile_split<true, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
-                else           tile_split<false, IPL>(T, cnt, sub, L, tb, ii, IS, eps2f, F, S);
+                tile_split<IPL>(T, cnt, sub, L, (int)tb, ii, IS, eps2f, nf, F, S);
             } else if constexpr (PREC == 3) {
-                if (need_mask) tile_sp<true, IPL>(T, cnt, sub, L, tb, ii, ISP, eps2f, F, S);
-                else           tile_sp<false, IPL>(T, cnt, sub, L, tb, ii, ISP, eps2f, F, S);
+                tile_sp<IPL>(T, cnt, sub, L, (int)tb, ii, ISP, eps2f, nf, F, S);
             } else {
-                if (need_mask) tile_mixed<true, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
-                else           tile_mixed<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2f, F, S);
+                tile_mixed<IPL>(T, cnt, sub, L, (int)tb, ii, I, eps2f, nf, F, S);
             }
         }
 
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
-            double out[7];
+            double out[kRows];
             finalize(S[q], out);
-            if constexpr (PREC == 3) {
-                // the jerk was summed in FP32 over the whole j-chunk
-                out[3] = (double)F[q].jx;
-                out[4] = (double)F[q].jy;
-                out[5] = (double)F[q].jz;
-            }
+            float ea = S[q].ea, ej = S[q].ej;
             if (L > 1) {
 #pragma unroll
                 for (int r = 0; r < 7; ++r) out[r] = shfl_sum(out[r], L);
+                ea = shfl_sum_f(ea, L);
+                ej = shfl_sum_f(ej, L);
+            }
+            out[kRows - 1] = pack_est(ea, ej);
+            if constexpr (PREC == 3) {
+                // the jerk: one FP32 running sum per lane over every L-th j of
+                // the whole range (the plan gives this mode one j-chunk), the
+                // L lanes' sums added in FP32 too; near pairs, if any, in FP64
+                float fj[3] = {F[q].jx, F[q].jy, F[q].jz};
+                if (L > 1) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) fj[r] = shfl_sum_f(fj[r], L);
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) out[3 + r] += (double)fj[r];
             }
             if (valid[q] && sub == 0) {
-                double* dst = a.partial + (int64_t)k * 7 * na + pp[q];
+                double* dst = a.partial + (int64_t)k * kRows * na + pp[q];
                 if (POT_ONLY) {
                     dst[6 * (int64_t)na] = out[6];
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 7; ++r) dst[r * (int64_t)na] = out[r];
+                    for (int r = 0; r < kRows; ++r) dst[r * (int64_t)na] = out[r];
                 }
             }
         }
@@ -678,7 +986,7 @@ __global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
 // Grid-stride over particles: one thread each when chunks are few, one
 // wave each when they are many (the launch shape does not depend on n_act).
 template <bool POT_ONLY>
-__device__ __forceinline__ void store_reduced(const SweepArgs& a, int p, const double s[7])
+__device__ __forceinline__ void store_reduced(const SweepArgs& a, int p, const double s[kRows])
 {
     const int64_t st = a.n_act_max;
     if (POT_ONLY) {
@@ -702,7 +1010,7 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
     const int na = a.plan->n_act;
     if (thread_reduce(a.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
-            double s[7];
+            double s[kRows];
             reduce_partials(a, na, p, s);
             store_reduced<POT_ONLY>(a, p, s);
         }
@@ -710,10 +1018,70 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
         const int lane = threadIdx.x & 63;
         const int wpb = kWG / 64;
         for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
-            double s[7];
+            double s[kRows];
             reduce_partials_wave(a, na, p, lane, s);
             if (lane == 0) store_reduced<POT_ONLY>(a, p, s);
         }
+    }
+}
+
+// The reduce of a mixed sweep with refinement: stores every particle's
+// mixed sums and compacts, per unit (a round of a workgroup), the
+// positions whose error estimate is too large; refine_plan_kernel then
+// lists them and plans the FP64 refine sweep.  Rounds run with uniform
+// trip counts over the workgroup (the compaction synchronises it).
+__global__ void __launch_bounds__(kWG) reduce_flag_kernel(SweepArgs a)
+{
+    const int na = a.plan->n_act;
+    if (thread_reduce(a.plan->s_max, na)) {
+        for (int u = blockIdx.x; u * kWG < na; u += gridDim.x) {
+            const int base = u * kWG;
+            const int p = base + (int)threadIdx.x;
+            bool flag = false;
+            if (p < na) {
+                double s[kRows];
+                reduce_partials(a, na, p, s);
+                store_reduced<false>(a, p, s);
+                flag = needs_refine(a, s);
+            }
+            flag_unit(a, u, base, p, p < na, flag);
+        }
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int wpb = kWG / 64;
+        for (int u = blockIdx.x; u * wpb < na; u += gridDim.x) {
+            const int base = u * wpb;
+            const int p = base + (int)(threadIdx.x >> 6);
+            bool flag = false;
+            if (p < na) {
+                double s[kRows];
+                reduce_partials_wave(a, na, p, lane, s);
+                if (lane == 0) store_reduced<false>(a, p, s);
+                flag = needs_refine(a, s);
+            }
+            flag_unit(a, u, base, p, p < na && lane == 0, flag);
+        }
+    }
+}
+
+// One workgroup: the refine list and the plan of the refine sweep ra.
+__global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs ra)
+{
+    const int na = a.plan->n_act;
+    const int unit = thread_reduce(a.plan->s_max, na) ? kWG : kWG / 64;
+    const int32_t cnt = build_refine_list(a, ra, na, unit);
+    if (threadIdx.x == 0 && a.counters && cnt > 0)
+        atomicAdd((unsigned long long*)&a.counters[5], (unsigned long long)cnt);
+}
+
+// Writes the refined sums of the flagged particles over their mixed ones.
+__global__ void __launch_bounds__(kWG) refine_scatter_kernel(SweepArgs a, SweepArgs ra)
+{
+    const int cnt = ra.plan->n_act;
+    for (int k = blockIdx.x * kWG + threadIdx.x; k < cnt; k += gridDim.x * kWG) {
+        double s[kRows];
+        reduce_partials(ra, cnt, k, s);
+        store_reduced<false>(a, a.ref_p[k], s);
     }
 }
 
@@ -771,34 +1139,79 @@ int max_plan_items(const SweepArgs& a)
     return best > 0 ? best : 1;
 }
 
-hipError_t launch_select_sweep(const SweepArgs& a_in, int precision, int variant, int grid,
+// Launches the sweep kernel(s) of one force sweep.  The mixed precisions
+// sweep systems of fewer than fp64_below particles in FP64 (at those sizes
+// the FP64 sweep is as fast as the FP32 one with its near field, and
+// exact): a single system takes one kernel or the other, and an ensemble
+// whose cluster sizes straddle the threshold takes both, each kernel doing
+// the work items of its kind of cluster.  Both kernels share the plan,
+// which fixes the active particles per lane: the FP64 kernel is the
+// instantiation with the mixed variant's count.
+void launch_sweep_kernels(SweepArgs a, int precision, int variant, int grid, bool pot_only,
+                          bool sel, hipStream_t st)
+{
+    a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
+    auto go = [&](int prec, int kind) {
+        a.kind = kind;
+        SweepFn f = sel ? sweep_sel_fn(prec, variant) : sweep_fn(prec, variant, pot_only);
+        hipLaunchKernelGGL(f, dim3(grid), dim3(kWG), 0, st, a);
+    };
+    const bool mixed = !pot_only && (precision == 1 || precision == 2);
+    if (!mixed) {
+        go(precision, 0);
+    } else if (a.n_cmax < a.fp64_below) {
+        go(0, 0);                          // every system is small
+    } else if (a.n_clusters == 1 || a.fp64_below <= 1) {
+        go(precision, 0);                  // none is
+    } else {
+        go(precision, 1);
+        go(0, 2);
+    }
+}
+
+hipError_t launch_select_sweep(const SweepArgs& a, int precision, int variant, int grid,
                                hipStream_t st)
 {
-    SweepArgs a = a_in;
-    a.ipl = (variant & 1) ? 2 : 1;
-    hipLaunchKernelGGL(sweep_sel_fn(precision, variant), dim3(grid), dim3(kWG), 0, st, a);
+    launch_sweep_kernels(a, precision, variant, grid, false, true, st);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_only(const SweepArgs& a_in, int precision, int variant, int grid,
+hipError_t launch_sweep_only(const SweepArgs& a, int precision, int variant, int grid,
                              hipStream_t st)
 {
-    SweepArgs a = a_in;
-    a.ipl = (variant & 1) ? 2 : 1;
-    hipLaunchKernelGGL(sweep_fn(precision, variant, false), dim3(grid), dim3(kWG), 0, st, a);
+    launch_sweep_kernels(a, precision, variant, grid, false, false, st);
     return hipGetLastError();
 }
 
-hipError_t launch_force(const SweepArgs& a_in, int precision, int variant,
+// Flagging reduce and FP64 refine sweep (both launch forms).
+hipError_t launch_reduce_refine(const SweepArgs& a_in, const SweepArgs& ra_in, int variant,
+                                int grid, hipStream_t st)
+{
+    SweepArgs a = a_in, ra = ra_in;
+    a.ipl = ra.ipl = (variant & 1) ? 2 : 1;
+    hipLaunchKernelGGL(reduce_flag_kernel, dim3(reduce_grid(a.n_act_max)), dim3(kWG), 0, st, a);
+    hipLaunchKernelGGL(refine_plan_kernel, dim3(1), dim3(kWG), 0, st, a, ra);
+    // the FP64 kernel with the mixed variant's particles per lane (the plan
+    // was made for that count)
+    launch_sweep_kernels(ra, 0, variant & 1, grid, false, false, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const SweepArgs& a_in, const SweepArgs* ra, int precision, int variant,
                         int grid, bool pot_only, hipStream_t st)
 {
     SweepArgs a = a_in;
     a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
-    hipLaunchKernelGGL(sweep_fn(precision, variant, pot_only), dim3(grid), dim3(kWG), 0, st, a);
+    launch_sweep_kernels(a, precision, variant, grid, pot_only, false, st);
     const int rgrid = reduce_grid(a.n_act_max);
     if (pot_only) {
         hipLaunchKernelGGL(reduce_kernel<true>, dim3(rgrid), dim3(kWG), 0, st, a);
+    } else if (ra && a.refine) {
+        launch_reduce_refine(a, *ra, variant, grid, st);
+        SweepArgs r = *ra;
+        r.ipl = a.ipl;
+        hipLaunchKernelGGL(refine_scatter_kernel, dim3(rgrid), dim3(kWG), 0, st, a, r);
     } else {
         hipLaunchKernelGGL(reduce_kernel<false>, dim3(rgrid), dim3(kWG), 0, st, a);
     }

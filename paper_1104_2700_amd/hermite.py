@@ -84,6 +84,8 @@ _SIGS = {
     "hermite_counters": ([_P, ctypes.POINTER(_i64), _P]),
     "hermite_block_histogram": ([_P, ctypes.POINTER(_i64), _P]),
     "hermite_get_tuning": ([_P, ctypes.c_int, _PT]),
+    "hermite_set_mixed_policy": ([_P, ctypes.c_int, _d, _i64]),
+    "hermite_get_mixed_policy": ([_P, ctypes.c_int, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
     "hermite_set_tuning": ([_P, ctypes.c_int, _PT]),
     "hermite_autotune": ([_P, _PS, _PC, _d, ctypes.c_int, _i32, ctypes.c_char_p, _P]),
     "hermite_load_tuning": ([_P, ctypes.c_char_p, ctypes.c_int, _i64, _i32]),
@@ -313,9 +315,10 @@ class Context:
         return True
 
     def counters(self, stream=None):
-        out = (_i64 * 5)()
+        out = (_i64 * 6)()
         _check(lib.hermite_counters(self.h, out, _stream(stream)), "hermite_counters")
-        return dict(zip(("steps", "interactions", "clamped", "T", "n_act"), list(out)))
+        return dict(zip(("steps", "interactions", "clamped", "T", "n_act", "refined"),
+                        list(out)))
 
     def sync(self, stream=None):
         _check(lib.hermite_sync(self.h, _stream(stream)), "hermite_sync")
@@ -326,6 +329,17 @@ class Context:
         _check(lib.hermite_get_tuning(self.h, int(precision), ctypes.byref(t)),
                "hermite_get_tuning")
         return t
+
+    def set_mixed_policy(self, precision, near_factor, fp64_below):
+        _check(lib.hermite_set_mixed_policy(self.h, int(precision), float(near_factor),
+                                            int(fp64_below)), "hermite_set_mixed_policy")
+
+    def get_mixed_policy(self, precision):
+        """Returns (near_factor, fp64_below)."""
+        f, b = _d(0.0), _i64(0)
+        _check(lib.hermite_get_mixed_policy(self.h, int(precision), ctypes.byref(f),
+                                            ctypes.byref(b)), "hermite_get_mixed_policy")
+        return f.value, b.value
 
     def set_tuning(self, precision, tuning: CTuning):
         _check(lib.hermite_set_tuning(self.h, int(precision), ctypes.byref(tuning)),
