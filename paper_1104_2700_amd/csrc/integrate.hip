@@ -1032,16 +1032,15 @@ __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, Swee
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     const int64_t st = c.n_act_max;
     const int cnt = ra.plan->n_act;
-    for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
-        const int k = ra.ref_pos[p];
-        double a1[3], j1[3], pot1;
-        if (k >= 0) {
-            double s[kRows];
-            reduce_partials(ra, cnt, k, s);
-            a1[0] = s[0]; a1[1] = s[1]; a1[2] = s[2];
-            j1[0] = s[3]; j1[1] = s[4]; j1[2] = s[5];
-            pot1 = s[6];
-        } else {
+    const int lane = threadIdx.x & 63;
+    // rounds of whole waves: a flagged lane's refine chunks are summed by
+    // its wave together
+    for (int base = (blockIdx.x * kWG + (int)threadIdx.x) & ~63; base < na;
+         base += gridDim.x * kWG) {
+        const int p = base + lane;
+        const int k = p < na ? ra.ref_pos[p] : -1;
+        double a1[3], j1[3], pot1 = 0.0;
+        if (p < na) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 a1[d] = c.acc1[d * st + p];
@@ -1049,7 +1048,20 @@ __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, Swee
             }
             pot1 = c.pot1[p];
         }
-        correct_one(c, p, T, a1, j1, pot1, true);
+        uint64_t fl = __ballot(k >= 0);
+        while (fl) {
+            const int owner = __builtin_ctzll(fl);
+            fl &= fl - 1;
+            const int kf = __shfl(k, owner);
+            double s[kRows];
+            reduce_partials_wave(ra, cnt, kf, lane, s);
+            if (lane == owner) {
+                a1[0] = s[0]; a1[1] = s[1]; a1[2] = s[2];
+                j1[0] = s[3]; j1[1] = s[4]; j1[2] = s[5];
+                pot1 = s[6];
+            }
+        }
+        if (p < na) correct_one(c, p, T, a1, j1, pot1, true);
     }
 }
 

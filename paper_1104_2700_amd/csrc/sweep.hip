@@ -718,7 +718,7 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[kRows])
 // n <= kFusedSelMax; the active list stays in LDS) and computes the plan;
 // workgroup 0 publishes list, n_act, T, plan and counters for the corrector.
 template <int PREC, bool POT_ONLY, int IPL, bool SPLIT, bool SEL = false>
-__global__ void __launch_bounds__(kWG) sweep_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2) ? 3 : 1) sweep_kernel(SweepArgs a)
 {
     static_assert(!SEL || !POT_ONLY, "the fused selection is for block steps");
     static_assert(!SPLIT || (PREC == 1 || PREC == 2), "split form is for the mixed modes");
@@ -1074,14 +1074,17 @@ __global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs
         atomicAdd((unsigned long long*)&a.counters[5], (unsigned long long)cnt);
 }
 
-// Writes the refined sums of the flagged particles over their mixed ones.
+// Writes the refined sums of the flagged particles over their mixed ones
+// (a wave per particle: the refine sweep splits j into many chunks).
 __global__ void __launch_bounds__(kWG) refine_scatter_kernel(SweepArgs a, SweepArgs ra)
 {
     const int cnt = ra.plan->n_act;
-    for (int k = blockIdx.x * kWG + threadIdx.x; k < cnt; k += gridDim.x * kWG) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = kWG / 64;
+    for (int k = blockIdx.x * wpb + (int)(threadIdx.x >> 6); k < cnt; k += gridDim.x * wpb) {
         double s[kRows];
-        reduce_partials(ra, cnt, k, s);
-        store_reduced<false>(a, a.ref_p[k], s);
+        reduce_partials_wave(ra, cnt, k, lane, s);
+        if (lane == 0) store_reduced<false>(a, a.ref_p[k], s);
     }
 }
 
