@@ -184,6 +184,30 @@ int hermite_force_jerk(hermite_ctx* ctx, const hermite_state* s,
                        int32_t n_act_max, double eps2, int precision,
                        double* acc, double* jerk, double* pot, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * sweep of hermite_force_jerk without a context and without any
+ * allocation.  Same arguments and results as hermite_force_jerk with a
+ * fresh context's launch shape and mixed-precision policy, except that the
+ * device counters are not updated.  Its scratch (plan, cluster tables,
+ * partial sums, refinement lists) is one static device array of
+ * HERMITE_NOALLOC_SCRATCH_BYTES (about 43 MB) that each GPU the library
+ * runs on holds until the process ends; it limits a call to
+ * HERMITE_NOALLOC_MAX_ACTIVE active particles and
+ * HERMITE_NOALLOC_MAX_CLUSTERS clusters (EINVAL beyond).  The array's
+ * device address is looked up once per device, by hermite_create or else
+ * by the first call on that device.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race and give wrong results.  Nothing in it needs clearing between
+ * calls. */
+#define HERMITE_NOALLOC_MAX_ACTIVE   65536
+#define HERMITE_NOALLOC_MAX_CLUSTERS 1024
+#define HERMITE_NOALLOC_SCRATCH_BYTES 43094540
+int hermite_force_jerk_noalloc(const hermite_state* s, const hermite_clusters* cl,
+                               const int32_t* idx, const int32_t* n_act_dev,
+                               int32_t n_act_max, double eps2, int precision,
+                               double* acc, double* jerk, double* pot, void* stream);
+
 /* Procedure steps 5-8 with the snap/crackle, corrector and timestep
  * equations of Section 2: for each active i (idx, n_act as above, T as
  * in hermite_predict), from s->xp, s->vp, the old s->a, s->j and the new

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -186,15 +187,20 @@ int check_dt(const hermite_dt_params* p, int tick_bits)
 // workgroup of the grid.
 // Chosen from a sweep of these parameters over active counts 256 ... 65536
 // at N = 65536 on gfx950; hermite_autotune refines it per size.
-hermite_tuning default_tuning(const hermite_ctx* c, int precision)
+hermite_tuning default_tuning_for(int n_cu)
 {
-    (void)precision;
     hermite_tuning t;
     t.variant = 1;
     t.wg_per_cu = 5;
-    t.target_lanes = c->n_cu * t.wg_per_cu * kWG;
+    t.target_lanes = n_cu * t.wg_per_cu * kWG;
     t.min_j_per_lane = 4;
     return t;
+}
+
+hermite_tuning default_tuning(const hermite_ctx* c, int precision)
+{
+    (void)precision;
+    return default_tuning_for(c->n_cu);
 }
 
 // Mixed-precision policy (hermite_set_mixed_policy).  Near-field radius
@@ -218,22 +224,48 @@ int64_t default_fp64_below(int precision)
     return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 8192 : 0;
 }
 
-// Fills the sweep arguments and makes sure the scratch they point to exists.
-int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
-                  const double* xp, const double* vp, const int32_t* idx,
-                  const int32_t* n_act_dev, int32_t n_act_max, double eps2, int precision,
-                  const hermite_tuning& tu, double* acc, double* jerk, double* pot,
-                  SweepArgs* a)
+// Device scratch of one force sweep and of its refinement, as pointers
+// (context buffers, or the static scratch of hermite_force_jerk_noalloc).
+struct SweepScratch {
+    SweepPlan* plan;
+    int32_t *act_start, *act_cnt, *chunks, *item_off;   // [C], item_off [C+1]
+    double* partial;
+    int64_t partial_cap;                                // doubles
+    int32_t *ref_pos, *ref_idx, *ref_p, *ref_tmp;       // [n_act_max]
+    int32_t *ref_ucnt, *ref_ccnt;                       // [n_act_max / 4 + 1], [C]
+    SweepPlan* rplan;
+    int32_t *ract_start, *ract_cnt, *rchunks, *ritem_off;
+    double* rpartial;
+    int64_t rpartial_cap;
+};
+
+// Partial-sum capacity of a sweep and of its refine sweep (doubles) for an
+// active count: room for 32 and 4 j-chunks of every active particle.
+int64_t partial_cap_for(int32_t n_act_max)
 {
-    const int C = cl ? cl->n_clusters : 1;
-    CHECK(ensure(c, c->plan, sizeof(SweepPlan)));
-    CHECK(ensure(c, c->act_start, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->act_cnt, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->chunks, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->item_off, sizeof(int32_t) * (C + 1)));
-    const int64_t cap = (int64_t)kRows * 32 * std::max<int64_t>(n_act_max, 4096);
-    CHECK(ensure(c, c->partial, sizeof(double) * cap));
-    CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
+    return (int64_t)kRows * 32 * std::max<int64_t>(n_act_max, 4096);
+}
+
+int64_t rpartial_cap_for(int32_t n_act_max)
+{
+    return (int64_t)kRows * 4 * std::max<int64_t>(n_act_max, 4096);
+}
+
+// True when a sweep of this precision and these systems runs the FP64
+// refinement: the mixed precisions, when some system is swept in FP32.
+bool uses_refine(int precision, int64_t n_cmax, int64_t fp64_below)
+{
+    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) && n_cmax >= fp64_below;
+}
+
+// Fills the sweep arguments from a state, launch shape, mixed policy and
+// scratch (no allocation).
+void fill_sweep(const SweepScratch& sc, const hermite_state* s, const hermite_clusters* cl,
+                const double* xp, const double* vp, const int32_t* idx,
+                const int32_t* n_act_dev, int32_t n_act_max, double eps2, int precision,
+                const hermite_tuning& tu, double near_factor, int64_t fp64_below,
+                int64_t* counters, double* acc, double* jerk, double* pot, SweepArgs* a)
+{
     std::memset(a, 0, sizeof *a);
     a->xp = xp;
     a->vp = vp;
@@ -242,76 +274,57 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     a->idx = idx;
     a->n_act_dev = n_act_dev;
     a->n_act_max = n_act_max;
-    a->n_clusters = C;
+    a->n_clusters = cl ? cl->n_clusters : 1;
     a->offsets = cl ? cl->offsets : nullptr;
     a->eps2_c = cl ? cl->eps2 : nullptr;
     a->eps2 = eps2;
     a->n_cmax = cl ? cl->max_size : s->n;
-    a->plan = (SweepPlan*)c->plan.p;
-    a->act_start = (int32_t*)c->act_start.p;
-    a->act_cnt = (int32_t*)c->act_cnt.p;
-    a->chunks = (int32_t*)c->chunks.p;
-    a->item_off = (int32_t*)c->item_off.p;
-    a->partial = (double*)c->partial.p;
-    a->partial_cap = (int64_t)(c->partial.bytes / sizeof(double));
+    a->plan = sc.plan;
+    a->act_start = sc.act_start;
+    a->act_cnt = sc.act_cnt;
+    a->chunks = sc.chunks;
+    a->item_off = sc.item_off;
+    a->partial = sc.partial;
+    a->partial_cap = sc.partial_cap;
     a->target_lanes = tu.target_lanes;
     a->min_j_per_lane = tu.min_j_per_lane;
-    a->near_factor = precision == HERMITE_FP64 ? 0.0 : c->near_factor[precision];
-    a->fp64_below = precision == HERMITE_FP64 ? 0 : c->fp64_below[precision];
-    // refinement for the mixed precisions that sweep some system in FP32
-    a->refine = ((precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) &&
-                 a->n_cmax >= a->fp64_below) ? 1 : 0;
+    a->near_factor = precision == HERMITE_FP64 ? 0.0 : near_factor;
+    a->fp64_below = precision == HERMITE_FP64 ? 0 : fp64_below;
+    a->refine = uses_refine(precision, a->n_cmax, a->fp64_below) ? 1 : 0;
     if (a->refine) {
-        const size_t na = (size_t)std::max<int32_t>(n_act_max, 1);
-        CHECK(ensure(c, c->ref_pos, sizeof(int32_t) * na));
-        CHECK(ensure(c, c->ref_idx, sizeof(int32_t) * na));
-        CHECK(ensure(c, c->ref_p, sizeof(int32_t) * na));
-        CHECK(ensure(c, c->ref_tmp, sizeof(int32_t) * na));
-        CHECK(ensure(c, c->ref_ucnt, sizeof(int32_t) * (na / (kWG / 64) + 1)));
-        CHECK(ensure(c, c->ref_ccnt, sizeof(int32_t) * (size_t)C));
-        a->ref_pos = (int32_t*)c->ref_pos.p;
-        a->ref_idx = (int32_t*)c->ref_idx.p;
-        a->ref_p = (int32_t*)c->ref_p.p;
-        a->ref_tmp = (int32_t*)c->ref_tmp.p;
-        a->ref_ucnt = (int32_t*)c->ref_ucnt.p;
-        a->ref_ccnt = (int32_t*)c->ref_ccnt.p;
+        a->ref_pos = sc.ref_pos;
+        a->ref_idx = sc.ref_idx;
+        a->ref_p = sc.ref_p;
+        a->ref_tmp = sc.ref_tmp;
+        a->ref_ucnt = sc.ref_ucnt;
+        a->ref_ccnt = sc.ref_ccnt;
     }
     a->one_chunk = precision == HERMITE_MIXED_SP ? 1 : 0;
-    a->counters = (int64_t*)c->counters.p;
+    a->counters = counters;
     a->acc = acc;
     a->jerk = jerk;
     a->pot = pot;
-    return HERMITE_OK;
 }
 
 // The FP64 refine sweep of a mixed sweep with refinement: the same system
 // and prediction, the flagged particles (ref_idx) as its active list, and
-// scratch of its own (its plan is made on the device by the flagging
-// reduce).  Its partial-sum buffer holds at least four chunks for every
-// active particle.
-int prepare_refine(hermite_ctx* c, const SweepArgs& a, SweepArgs* ra)
+// scratch of its own (its plan is made on the device after the flagging
+// reduce).
+void fill_refine(const SweepScratch& sc, const SweepArgs& a, SweepArgs* ra)
 {
-    const int C = a.n_clusters;
-    CHECK(ensure(c, c->rplan, sizeof(SweepPlan)));
-    CHECK(ensure(c, c->ract_start, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->ract_cnt, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->rchunks, sizeof(int32_t) * C));
-    CHECK(ensure(c, c->ritem_off, sizeof(int32_t) * (C + 1)));
-    const int64_t cap = (int64_t)kRows * 4 * std::max<int64_t>(a.n_act_max, 4096);
-    CHECK(ensure(c, c->rpartial, sizeof(double) * cap));
     *ra = a;
     ra->idx = a.ref_idx;
     ra->n_act_dev = nullptr;
-    ra->plan = (SweepPlan*)c->rplan.p;
-    ra->act_start = (int32_t*)c->ract_start.p;
-    ra->act_cnt = (int32_t*)c->ract_cnt.p;
-    ra->chunks = (int32_t*)c->rchunks.p;
-    ra->item_off = (int32_t*)c->ritem_off.p;
+    ra->plan = sc.rplan;
+    ra->act_start = sc.ract_start;
+    ra->act_cnt = sc.ract_cnt;
+    ra->chunks = sc.rchunks;
+    ra->item_off = sc.ritem_off;
     ra->act_cluster = nullptr;
-    // with clusters the flagging reduce writes each cluster's run start
-    ra->sel_clusters = C > 1 ? 1 : 0;
-    ra->partial = (double*)c->rpartial.p;
-    ra->partial_cap = (int64_t)(c->rpartial.bytes / sizeof(double));
+    // with clusters the refine list's builder writes each cluster's run start
+    ra->sel_clusters = a.n_clusters > 1 ? 1 : 0;
+    ra->partial = sc.rpartial;
+    ra->partial_cap = sc.rpartial_cap;
     ra->refine = 0;
     ra->near_factor = 0.0;
     ra->fp64_below = 0;
@@ -322,6 +335,84 @@ int prepare_refine(hermite_ctx* c, const SweepArgs& a, SweepArgs* ra)
     ra->sel_na_out = nullptr;
     ra->sel_T_out = nullptr;
     ra->acc = ra->jerk = ra->pot = nullptr;
+}
+
+// The context's scratch for a sweep of C systems and n_act_max active
+// particles (allocated or grown as needed).
+int ctx_scratch(hermite_ctx* c, int C, int32_t n_act_max, bool refine, SweepScratch* sc)
+{
+    std::memset(sc, 0, sizeof *sc);
+    CHECK(ensure(c, c->plan, sizeof(SweepPlan)));
+    CHECK(ensure(c, c->act_start, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->act_cnt, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->chunks, sizeof(int32_t) * C));
+    CHECK(ensure(c, c->item_off, sizeof(int32_t) * (C + 1)));
+    CHECK(ensure(c, c->partial, sizeof(double) * partial_cap_for(n_act_max)));
+    sc->plan = (SweepPlan*)c->plan.p;
+    sc->act_start = (int32_t*)c->act_start.p;
+    sc->act_cnt = (int32_t*)c->act_cnt.p;
+    sc->chunks = (int32_t*)c->chunks.p;
+    sc->item_off = (int32_t*)c->item_off.p;
+    sc->partial = (double*)c->partial.p;
+    sc->partial_cap = (int64_t)(c->partial.bytes / sizeof(double));
+    if (refine) {
+        const size_t na = (size_t)std::max<int32_t>(n_act_max, 1);
+        CHECK(ensure(c, c->ref_pos, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_idx, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_p, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_tmp, sizeof(int32_t) * na));
+        CHECK(ensure(c, c->ref_ucnt, sizeof(int32_t) * (na / (kWG / 64) + 1)));
+        CHECK(ensure(c, c->ref_ccnt, sizeof(int32_t) * (size_t)C));
+        CHECK(ensure(c, c->rplan, sizeof(SweepPlan)));
+        CHECK(ensure(c, c->ract_start, sizeof(int32_t) * C));
+        CHECK(ensure(c, c->ract_cnt, sizeof(int32_t) * C));
+        CHECK(ensure(c, c->rchunks, sizeof(int32_t) * C));
+        CHECK(ensure(c, c->ritem_off, sizeof(int32_t) * (C + 1)));
+        CHECK(ensure(c, c->rpartial, sizeof(double) * rpartial_cap_for(n_act_max)));
+        sc->ref_pos = (int32_t*)c->ref_pos.p;
+        sc->ref_idx = (int32_t*)c->ref_idx.p;
+        sc->ref_p = (int32_t*)c->ref_p.p;
+        sc->ref_tmp = (int32_t*)c->ref_tmp.p;
+        sc->ref_ucnt = (int32_t*)c->ref_ucnt.p;
+        sc->ref_ccnt = (int32_t*)c->ref_ccnt.p;
+        sc->rplan = (SweepPlan*)c->rplan.p;
+        sc->ract_start = (int32_t*)c->ract_start.p;
+        sc->ract_cnt = (int32_t*)c->ract_cnt.p;
+        sc->rchunks = (int32_t*)c->rchunks.p;
+        sc->ritem_off = (int32_t*)c->ritem_off.p;
+        sc->rpartial = (double*)c->rpartial.p;
+        sc->rpartial_cap = (int64_t)(c->rpartial.bytes / sizeof(double));
+    }
+    return HERMITE_OK;
+}
+
+// Fills the sweep arguments and makes sure the context scratch they point
+// to exists (refinement scratch included, when the sweep refines).
+int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                  const double* xp, const double* vp, const int32_t* idx,
+                  const int32_t* n_act_dev, int32_t n_act_max, double eps2, int precision,
+                  const hermite_tuning& tu, double* acc, double* jerk, double* pot,
+                  SweepArgs* a)
+{
+    const int C = cl ? cl->n_clusters : 1;
+    const double nfac = precision == HERMITE_FP64 ? 0.0 : c->near_factor[precision];
+    const int64_t f64b = precision == HERMITE_FP64 ? 0 : c->fp64_below[precision];
+    const bool refine = uses_refine(precision, cl ? cl->max_size : s->n, f64b);
+    SweepScratch sc;
+    CHECK(ctx_scratch(c, C, n_act_max, refine, &sc));
+    CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
+    fill_sweep(sc, s, cl, xp, vp, idx, n_act_dev, n_act_max, eps2, precision, tu, nfac, f64b,
+               (int64_t*)c->counters.p, acc, jerk, pot, a);
+    return HERMITE_OK;
+}
+
+// The refine sweep's arguments from the context scratch (which
+// prepare_sweep has made for a refining sweep).
+int prepare_refine(hermite_ctx* c, const SweepArgs& a, SweepArgs* ra)
+{
+    SweepScratch sc;
+    CHECK(ctx_scratch(c, a.n_clusters, a.n_act_max, true, &sc));
+    fill_refine(sc, a, ra);
     return HERMITE_OK;
 }
 
@@ -546,6 +637,95 @@ std::string step_key(const hermite_state* s, const hermite_clusters* cl, double 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of hermite_force_jerk_noalloc: one file-scope device array, laid
+// out as the context scratch of a sweep of at most kNoAllocMaxActive active
+// particles in at most kNoAllocMaxClusters systems (partial sums for 8
+// j-chunks of every active particle, 2 for the refine sweep).  Each device
+// holds its own copy, at the address hipGetSymbolAddress gives on it.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxActive = HERMITE_NOALLOC_MAX_ACTIVE;
+constexpr int kNoAllocMaxClusters = HERMITE_NOALLOC_MAX_CLUSTERS;
+constexpr int64_t kNoAllocPartial = (int64_t)kRows * 8 * kNoAllocMaxActive;    // doubles
+constexpr int64_t kNoAllocRPartial = (int64_t)kRows * 2 * kNoAllocMaxActive;   // doubles
+constexpr int64_t kNoAllocInts =
+    2 * (3 * (int64_t)kNoAllocMaxClusters + (kNoAllocMaxClusters + 1)) +  // tables
+    4 * kNoAllocMaxActive + (kNoAllocMaxActive / (kWG / 64) + 1) +         // refine lists
+    kNoAllocMaxClusters;                                                    // per-cluster counts
+constexpr size_t kNoAllocBytes = sizeof(double) * (kNoAllocPartial + kNoAllocRPartial) +
+                                 2 * 256 +                                  // the two plans
+                                 sizeof(int32_t) * kNoAllocInts;
+static_assert(sizeof(SweepPlan) <= 256, "plan slot");
+static_assert(kNoAllocBytes == (size_t)HERMITE_NOALLOC_SCRATCH_BYTES, "header states the size");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+struct NoAllocDevice {
+    bool ready = false;
+    unsigned char* base = nullptr;   // the array's address on this device
+    int n_cu = 0;
+};
+
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[64];
+
+// Once per device, with it current: the array's address there (host code
+// must never pass the array's own name, a host-side stand-in) and the CU
+// count for the launch shape.
+int noalloc_init(int device, NoAllocDevice** out)
+{
+    if (device < 0 || device >= 64) return fail(HERMITE_ENODEV, "device %d not supported", device);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocDevice& d = g_noalloc[device];
+    if (!d.ready) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        int n_cu = 0;
+        HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+        d.base = (unsigned char*)ptr;
+        d.n_cu = n_cu;
+        d.ready = true;
+    }
+    *out = &d;
+    return HERMITE_OK;
+}
+
+// The SweepScratch views of the static array on one device.
+SweepScratch noalloc_carve(unsigned char* base)
+{
+    SweepScratch sc;
+    std::memset(&sc, 0, sizeof sc);
+    double* d = (double*)base;
+    sc.partial = d;
+    sc.partial_cap = kNoAllocPartial;
+    sc.rpartial = d + kNoAllocPartial;
+    sc.rpartial_cap = kNoAllocRPartial;
+    unsigned char* q = (unsigned char*)(d + kNoAllocPartial + kNoAllocRPartial);
+    sc.plan = (SweepPlan*)q;
+    sc.rplan = (SweepPlan*)(q + 256);
+    int32_t* i = (int32_t*)(q + 512);
+    const int C = kNoAllocMaxClusters;
+    sc.act_start = i;   i += C;
+    sc.act_cnt = i;     i += C;
+    sc.chunks = i;      i += C;
+    sc.item_off = i;    i += C + 1;
+    sc.ract_start = i;  i += C;
+    sc.ract_cnt = i;    i += C;
+    sc.rchunks = i;     i += C;
+    sc.ritem_off = i;   i += C + 1;
+    sc.ref_pos = i;     i += kNoAllocMaxActive;
+    sc.ref_idx = i;     i += kNoAllocMaxActive;
+    sc.ref_p = i;       i += kNoAllocMaxActive;
+    sc.ref_tmp = i;     i += kNoAllocMaxActive;
+    sc.ref_ucnt = i;    i += kNoAllocMaxActive / (kWG / 64) + 1;
+    sc.ref_ccnt = i;
+    return sc;
+}
+
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -572,6 +752,15 @@ int hermite_create(int device, hermite_ctx** out)
     }
     c->n_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    {
+        // set-up of hermite_force_jerk_noalloc's scratch on this device
+        NoAllocDevice* nd = nullptr;
+        const int rc0 = noalloc_init(device, &nd);
+        if (rc0 != HERMITE_OK) {
+            delete c;
+            return rc0;
+        }
+    }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(HERMITE_EHIP, "hipStreamCreateWithFlags failed");
@@ -668,6 +857,46 @@ int hermite_force_jerk(hermite_ctx* c, const hermite_state* s, const hermite_clu
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, precision, tu, acc,
                         jerk, pot, &a));
     return run_force(c, a, precision, tu, false, (hipStream_t)stream);
+}
+
+int hermite_force_jerk_noalloc(const hermite_state* s, const hermite_clusters* cl,
+                               const int32_t* idx, const int32_t* n_act_dev, int32_t n_act_max,
+                               double eps2, int precision, double* acc, double* jerk,
+                               double* pot, void* stream)
+{
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    if (n_act_max < 0 || n_act_max > s->n)
+        return fail(HERMITE_EINVAL, "n_act_max = %d out of range [0, n]", n_act_max);
+    if (n_act_max > kNoAllocMaxActive)
+        return fail(HERMITE_EINVAL,
+                    "n_act_max = %d exceeds the allocation-free limit of %lld active particles",
+                    n_act_max, (long long)kNoAllocMaxActive);
+    if (cl && cl->n_clusters > kNoAllocMaxClusters)
+        return fail(HERMITE_EINVAL,
+                    "%d clusters exceed the allocation-free limit of %d", cl->n_clusters,
+                    kNoAllocMaxClusters);
+    if (n_act_max == 0) return HERMITE_OK;
+    if (!idx && n_act_max != s->n)
+        return fail(HERMITE_EINVAL, "identity index list needs n_act_max == n");
+    if (!acc || !jerk) return fail(HERMITE_EINVAL, "null output pointer");
+    int device = 0;
+    HIP_OK(hipGetDevice(&device));
+    NoAllocDevice* nd = nullptr;
+    CHECK(noalloc_init(device, &nd));
+    const SweepScratch sc = noalloc_carve(nd->base);
+    const hermite_tuning tu = default_tuning_for(nd->n_cu);
+    SweepArgs a, ra;
+    fill_sweep(sc, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, precision, tu,
+               default_near_factor(precision), default_fp64_below(precision), nullptr, acc,
+               jerk, pot, &a);
+    if (a.refine) fill_refine(sc, a, &ra);
+    const int grid = std::max(1, nd->n_cu * tu.wg_per_cu);
+    HIP_OK(launch_force(a, a.refine ? &ra : nullptr, precision, tu.variant, grid, false,
+                        (hipStream_t)stream));
+    return HERMITE_OK;
 }
 
 int hermite_correct(hermite_ctx* c, const hermite_state* s, const int32_t* idx,

@@ -73,6 +73,7 @@ _SIGS = {
     "hermite_select_block": ([_P, _PS, _P, _P, _P, _i64, _P]),
     "hermite_predict": ([_P, _PS, _P, _i64, _P, _P]),
     "hermite_force_jerk": ([_P, _PS, _PC, _P, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _P]),
+    "hermite_force_jerk_noalloc": ([_PS, _PC, _P, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _P]),
     "hermite_correct": ([_P, _PS, _P, _P, _i32, _P, _i64, _P, _P, _P, _PD, _P, _P]),
     "hermite_init_dt": ([_P, _PS, _PD, _P]),
     "hermite_check_finite": ([_P, _PS, _P]),
@@ -98,6 +99,10 @@ lib.hermite_last_error.argtypes = []
 lib.hermite_last_error.restype = ctypes.c_char_p
 
 
+NOALLOC_MAX_ACTIVE = 65536
+NOALLOC_MAX_CLUSTERS = 1024
+
+
 class HermiteError(RuntimeError):
     def __init__(self, code, func):
         msg = lib.hermite_last_error().decode(errors="replace")
@@ -118,6 +123,21 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def force_jerk_noalloc(s, idx, eps2, precision, acc, jerk, pot=None, n_act_dev=None,
+                       n_act_max=None, clusters=None, stream=None):
+    """hermite_force_jerk_noalloc: the force sweep with no context and no
+    allocation (outputs must be given)."""
+    if n_act_max is None:
+        n_act_max = s.n if idx is None else int(idx.shape[0])
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    _check(lib.hermite_force_jerk_noalloc(ctypes.byref(s.c()), _cl(clusters), _ptr(idx),
+                                          _ptr(n_act_dev), int(n_act_max), float(eps2),
+                                          int(precision), _ptr(acc), _ptr(jerk), _ptr(pot),
+                                          _stream(stream)), "hermite_force_jerk_noalloc")
+    return acc, jerk, pot
 
 
 class State:

@@ -1,0 +1,95 @@
+"""The allocation-free sweep entry point (hermite_force_jerk_noalloc)
+against hermite_force_jerk on the same inputs, through the C ABI: two
+calls in a row, the second smaller, to the parity bars of the two paths
+(FP64 1e-13, mixed 1e-6 relative per particle); free device memory does
+not change across calls; sizes beyond the static scratch are refused."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1104_2700_amd import hermite
+    return hermite
+
+
+def _state(H, n, seed):
+    from paper_1104_2700_amd import inputs
+    x, v, m = inputs.plummer(n, seed)
+    s = H.State(x, v, m)
+    s.xp.copy_(s.x)
+    s.vp.copy_(s.v)
+    return s
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 1e-6), (2, 1e-6), (3, 1e-6)])
+def test_noalloc_matches_force_jerk(H, prec, tol):
+    ctx = H.Context(0)
+    try:
+        cases = [(20000, None, 61), (5000, 777, 62)]      # second call smaller
+        outs = {}
+        for k, (n, n_act, seed) in enumerate(cases):
+            s = _state(H, n, seed)
+            eps2 = (4.0 / n) ** 2
+            if n_act is None:
+                idx = None
+                na = n
+            else:
+                rng = np.random.default_rng(seed)
+                idx = torch.from_numpy(np.sort(rng.choice(n, n_act, replace=False))
+                                       .astype(np.int32)).cuda()
+                na = n_act
+            acc = torch.empty(3, na, dtype=torch.float64, device="cuda")
+            jrk = torch.empty_like(acc)
+            pot = torch.empty(na, dtype=torch.float64, device="cuda")
+            H.force_jerk_noalloc(s, idx, eps2, prec, acc, jrk, pot)
+            ra, rj, rp = ctx.force_jerk(s, idx, eps2, prec)
+            torch.cuda.synchronize()
+            A, J, P = acc.cpu().numpy(), jrk.cpu().numpy(), pot.cpu().numpy()
+            RA, RJ, RP = ra.cpu().numpy(), rj.cpu().numpy(), rp.cpu().numpy()
+            assert _rel(A, RA).max() <= tol, (k, _rel(A, RA).max())
+            assert _rel(J, RJ).max() <= tol, (k, _rel(J, RJ).max())
+            assert np.abs(P - RP).max() <= tol * np.abs(RP).max()
+            outs[k] = (A, J, P)
+    finally:
+        ctx.close()
+
+
+def test_noalloc_leaves_free_memory_unchanged(H):
+    n = 30000
+    s = _state(H, n, 63)
+    eps2 = (4.0 / n) ** 2
+    acc = torch.empty(3, n, dtype=torch.float64, device="cuda")
+    jrk = torch.empty_like(acc)
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    H.force_jerk_noalloc(s, None, eps2, H.MIXED, acc, jrk, pot)      # warm-up
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for prec in (0, 1, 2, 3):
+        H.force_jerk_noalloc(s, None, eps2, prec, acc, jrk, pot)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch(H):
+    n = H.NOALLOC_MAX_ACTIVE + 1
+    s = _state(H, n, 64)
+    acc = torch.empty(3, n, dtype=torch.float64, device="cuda")
+    jrk = torch.empty_like(acc)
+    with pytest.raises(H.HermiteError) as err:
+        H.force_jerk_noalloc(s, None, 1e-8, H.FP64, acc, jrk)
+    assert err.value.code == H.EINVAL and "allocation-free limit" in str(err.value)
+    # a sub-list within the limit runs
+    idx = torch.arange(0, n, 2, dtype=torch.int32, device="cuda")
+    out = torch.empty(3, idx.shape[0], dtype=torch.float64, device="cuda")
+    H.force_jerk_noalloc(s, idx, 1e-8, H.FP64, out, torch.empty_like(out))
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
