@@ -30,14 +30,17 @@ def check_fp64(name, got, ref, cond, n_sum, tol=TOL_FP64):
     return int(np.sum(err > tol * mag))
 
 
-def check_mixed(name, got, ref, cond, tol=TOL_MIXED, cond_factor=16.0):
-    """Mixed parity: |d| <= tol |ref|, or, where the pair sum cancels, the
-    FP32 pair-arithmetic bound |d| <= cond_factor u32 sum_j |term_j|.
+def check_mixed(name, got, ref, cond, tol=TOL_MIXED, cond_factor=4.0, max_second=0):
+    """Mixed parity: |d| <= tol |ref| for every particle, except that at most
+    max_second of them may instead meet |d| <= cond_factor u32 sum_j |term_j|.
 
-    cond_factor = 16: each pair term passes through about eight FP32
-    roundings (<= u32/2 each, so <= 4 u32 relative per term) and a 16-term
-    FP32 run sum adds <= 8 u32 of the run's absolute sum; 4 + 8 <= 16.
-    Returns (n_second_clause, worst relative error)."""
+    cond_factor = 4: rounding the FP64 differences to FP32 alone, with all
+    later arithmetic exact, stays within 4 u32 sum_j |term_j| on the N = 65536
+    Plummer sample (tests/test_mixed_tolerance.py).  The default policy
+    (near field in FP64, refinement of particles whose FP32 error estimate is
+    large) brings every particle under tol, so callers allow the second
+    clause only where a test's mode has no refinement (the paper-faithful
+    mode).  Returns (n_second_clause, worst relative error)."""
     got, ref = np.atleast_2d(got), np.atleast_2d(ref)
     err = np.linalg.norm(got - ref, axis=0)
     mag = np.linalg.norm(ref, axis=0)
@@ -45,7 +48,25 @@ def check_mixed(name, got, ref, cond, tol=TOL_MIXED, cond_factor=16.0):
     ok = (err <= tol * mag) | (err <= bound)
     rel = err / np.maximum(mag, 1e-300)
     assert np.all(ok), "%s: %d bad, worst rel %.3e" % (name, np.sum(~ok), rel.max())
-    return int(np.sum(err > tol * mag)), float(rel.max())
+    n_second = int(np.sum(err > tol * mag))
+    assert n_second <= max_second, "%s: %d particles above %.0e (allowed %d), worst %.3e" % (
+        name, n_second, tol, max_second, rel.max())
+    return n_second, float(rel.max())
+
+
+def fp32_policy(H, ctx, near_factor=3.0):
+    """Makes the mixed precisions sweep every system in FP32 (with their
+    near field and refinement), as they do for N >= 8192 by default; returns
+    the previous policies for restore_policy."""
+    saved = {p: ctx.get_mixed_policy(p) for p in (H.MIXED, H.MIXED_2F)}
+    for p in (H.MIXED, H.MIXED_2F):
+        ctx.set_mixed_policy(p, near_factor, 0)
+    return saved
+
+
+def restore_policy(ctx, saved):
+    for p, (f, b) in saved.items():
+        ctx.set_mixed_policy(p, f, b)
 
 
 def plummer_state(n, seed):

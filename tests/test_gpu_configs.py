@@ -1,0 +1,261 @@
+"""The benchmark configurations at their own sizes and inputs, through the
+C ABI, against the oracle.
+
+* The 256-cluster ensemble (673,038 particles, N_c 263 ... 8147, softening
+  4 / N_c per cluster): sampled sweeps in each cluster-size band and
+  lockstepped block steps (the union of clusters on one block timeline),
+  with the mixed precision sweeping in FP32 (its default policy sweeps
+  clusters this small in FP64, checked bit for bit against the FP64 path).
+* The N = 131072 Plummer sphere with a Salpeter mass spectrum, 10 % binary
+  members and softening 1e-5: a sampled sweep over singles and binary
+  members in both mixed precisions, and lockstepped block steps on a deep
+  block-timestep hierarchy (ticks of 2^-40, steps down to 2^-32).
+* The N = 1024 run to t = 1/8 (Section 4's energy study) in the mixed and
+  the paper-faithful precisions against the oracle's FP64 run.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import check_fp64, check_mixed, fp32_policy, restore_policy
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1104_2700_amd import hermite
+    return hermite
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _near_boundary(crit, rel):
+    crit = np.asarray(crit, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l2 = np.log2(crit)
+    return np.abs(l2 - np.rint(l2)) < rel / np.log(2)
+
+
+@pytest.fixture(scope="module")
+def ensemble():
+    from paper_1104_2700_amd import inputs
+    x, v, m, off, eps = inputs.ensemble()
+    return x, v, m, off, eps ** 2
+
+
+def _bands(off):
+    """Two clusters from each size band (< 1000, 1000-4000, > 4000)."""
+    sizes = np.diff(off)
+    picks = []
+    for lo, hi in ((0, 1000), (1000, 4000), (4000, 1 << 30)):
+        cs = np.nonzero((sizes >= lo) & (sizes < hi))[0]
+        picks += [int(cs[0]), int(cs[-1])]
+    return picks
+
+
+def test_ensemble_sampled_sweep(H, ctx, ensemble):
+    from oracle import oracle as O
+    x, v, m, off, eps2 = ensemble
+    cl = H.Clusters(off, eps2)
+    s = H.State(x, v, m)
+    s.xp.copy_(s.x)
+    s.vp.copy_(s.v)
+    A64, J64, P64 = ctx.force_jerk(s, None, 0.0, H.FP64, clusters=cl)
+    Ad, Jd, Pd = ctx.force_jerk(s, None, 0.0, H.MIXED, clusters=cl)
+    torch.cuda.synchronize()
+    # default policy: every cluster is below fp64_below -> the FP64 kernel
+    assert torch.equal(Ad, A64) and torch.equal(Jd, J64) and torch.equal(Pd, P64)
+    saved = fp32_policy(H, ctx)
+    try:
+        Am, Jm, Pm = ctx.force_jerk(s, None, 0.0, H.MIXED, clusters=cl)
+        torch.cuda.synchronize()
+    finally:
+        restore_policy(ctx, saved)
+    A64, J64, P64 = A64.cpu().numpy(), J64.cpu().numpy(), P64.cpu().numpy()
+    Am, Jm, Pm = Am.cpu().numpy(), Jm.cpu().numpy(), Pm.cpu().numpy()
+    rng = np.random.default_rng(4004)
+    for c in _bands(off):
+        lo, hi = int(off[c]), int(off[c + 1])
+        ids = np.sort(rng.choice(np.arange(lo, hi), min(256, hi - lo), replace=False))
+        ids = ids.astype(np.int32)
+        ra, rj, rp, cond = O.force(x, v, m, ids, eps2[c], j_range=(lo, hi), with_cond=True)
+        nc = hi - lo
+        check_fp64("acc%d" % c, A64[:, ids], ra, cond[0], nc)
+        check_fp64("jerk%d" % c, J64[:, ids], rj, cond[1], nc)
+        check_fp64("pot%d" % c, P64[ids][None], rp[None], cond[2], nc)
+        check_mixed("acc%d" % c, Am[:, ids], ra, cond[0])
+        check_mixed("jerk%d" % c, Jm[:, ids], rj, cond[1])
+        check_mixed("pot%d" % c, Pm[ids][None], rp[None], cond[2])
+
+
+def _lockstep(H, ctx, s, m, params, prec, steps, eps2_of, tb, k_min, k_max, eta, clusters,
+              off):
+    """Block steps in lockstep with the oracle, per cluster (or the whole
+    system), from the GPU's pre-step state: the same block time and active
+    list; the new forces within the precision's bar of the oracle's; and the
+    oracle's corrector, given the GPU's forces, reproduces the GPU's
+    corrected state (positions and velocities to rounding, step sizes
+    except at power-of-two ties of the criterion).  (The criterion
+    differences the forces over a step, so force errors of a few 1e-8 can
+    move it by more than a tie where the step is short; the corrector is
+    therefore checked on the GPU's own forces.)  Returns the number of
+    active particles seen and of step-size ties."""
+    from oracle import oracle as O
+    active = ties = 0
+    n = m.shape[0]
+    for step in range(steps):
+        pre = s.to_numpy()
+        T, idx = O.select(pre["t"], pre["dt"])
+        ctx.step(s, 0.0 if clusters is not None else eps2_of(0), params, prec, clusters=clusters)
+        cnt = ctx.counters()
+        g = s.to_numpy()
+        assert cnt["T"] == T and cnt["n_act"] == idx.shape[0]
+        assert np.array_equal(g["t"], np.where(np.isin(np.arange(n), idx), T, pre["t"]))
+        active += idx.shape[0]
+        ranges = [(0, n)] if off is None else list(zip(off[:-1], off[1:]))
+        for c, (lo, hi) in enumerate(ranges):
+            act = idx[(idx >= lo) & (idx < hi)]
+            if act.size == 0:
+                assert np.array_equal(g["x"][:, lo:hi], pre["x"][:, lo:hi])
+                continue
+            sub = {k: (pre[k][..., lo:hi].copy() if isinstance(pre[k], np.ndarray) else pre[k])
+                   for k in pre}
+            xp, vp = O.predict(sub["x"], sub["v"], sub["a"], sub["j"], sub["t"], T, tb)
+            la = (act - lo).astype(np.int32)
+            a1, j1, p1, cond = O.force(xp, vp, sub["m"], la, eps2_of(c), with_cond=True)
+            ga, gj, gp = g["a"][:, act], g["j"][:, act], g["pot"][act]
+            check_mixed("a", ga, a1, cond[0])
+            check_mixed("j", gj, j1, cond[1])
+            check_mixed("pot", gp[None], p1[None], cond[2])
+            crit = np.zeros(la.shape[0])
+            O.correct(sub, la, T, xp, vp, ga.copy(), gj.copy(), gp.copy(), eta, 0, k_min, k_max,
+                      crit_out=crit)
+            sc = np.abs(sub["x"]).max() + np.abs(sub["v"]).max()
+            assert np.abs(g["x"][:, lo:hi] - sub["x"]).max() <= 1e-13 * sc
+            assert np.abs(g["v"][:, lo:hi] - sub["v"]).max() <= 1e-13 * sc
+            assert np.array_equal(g["t"][lo:hi], sub["t"])
+            mism = g["dt"][lo:hi] != sub["dt"]
+            if mism.any():
+                pos = np.searchsorted(la, np.nonzero(mism)[0])
+                assert np.all(_near_boundary(crit[pos], 1e-9))
+                ties += int(mism.sum())
+                fixed = g["dt"].copy()
+                fixed[lo:hi] = sub["dt"]
+                s.dt.copy_(_dev(fixed))
+    return active, ties
+
+
+def test_ensemble_lockstep(H, ctx, ensemble):
+    x, v, m, off, eps2 = ensemble
+    cl = H.Clusters(off, eps2)
+    tb = 20
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s = H.State(x, v, m, tb)
+    ctx.initialize(s, 0.0, params, H.FP64, clusters=cl)
+    torch.cuda.synchronize()
+    saved = fp32_policy(H, ctx)
+    try:
+        active, ties = _lockstep(H, ctx, s, m, params, H.MIXED, 4, lambda c: eps2[c], tb, 3, 20,
+                                 0.02, cl, off)
+    finally:
+        restore_policy(ctx, saved)
+    assert active > 0 and ties <= 2
+
+
+@pytest.fixture(scope="module")
+def imf():
+    from paper_1104_2700_amd import inputs
+    x, v, m = inputs.plummer_imf_binaries(131072, 5)
+    return x, v, m, 1e-10
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_imf_binaries_sampled_sweep(H, ctx, imf, prec):
+    """Default policy (N = 131072 is swept in FP32): 512 single stars and
+    512 binary members (the last 10 % of the indices) within 1e-6 of the
+    oracle in acc, jerk and pot."""
+    from oracle import oracle as O
+    x, v, m, eps2 = imf
+    n = m.shape[0]
+    s = H.State(x, v, m)
+    s.xp.copy_(s.x)
+    s.vp.copy_(s.v)
+    acc, jrk, pot = ctx.force_jerk(s, None, eps2, prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5005)
+    n_bin = int(round(0.1 * n))
+    sample = np.sort(np.concatenate([rng.choice(n - n_bin, 512, replace=False),
+                                     n - n_bin + rng.choice(n_bin, 512, replace=False)]))
+    sample = sample.astype(np.int32)
+    ra, rj, rp, cond = O.force(x, v, m, sample, eps2, with_cond=True)
+    A, J, P = acc.cpu().numpy(), jrk.cpu().numpy(), pot.cpu().numpy()
+    check_mixed("acc", A[:, sample], ra, cond[0])
+    check_mixed("jerk", J[:, sample], rj, cond[1])
+    check_mixed("pot", P[sample][None], rp[None], cond[2])
+
+
+def test_imf_binaries_deep_hierarchy_lockstep(H, ctx, imf):
+    """Ticks of 2^-40 and steps down to 2^-32: the tight binaries get their
+    own short steps instead of a clamped floor; block steps in the
+    two-float mixed precision follow the oracle."""
+    x, v, m, eps2 = imf
+    tb, k_max = 40, 32
+    params = H.dt_params(0.02, H.DT_PAPER, 3, k_max)
+    s = H.State(x, v, m, tb)
+    c0 = ctx.counters()
+    ctx.initialize(s, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    dt = s.dt.cpu().numpy()
+    kmin_seen = tb - int(np.log2(dt.min()))
+    assert kmin_seen > 20        # deeper than the 2^-20 floor of the other configurations
+    active, ties = _lockstep(H, ctx, s, m, params, H.MIXED_2F, 4, lambda c: eps2, tb, 3, k_max,
+                             0.02, None, None)
+    assert active > 0 and ties <= 2
+
+
+@pytest.mark.parametrize("prec", [1, 3])
+def test_run_c1_mixed_energy_and_oracle(H, ctx, prec):
+    """Plummer N = 1024, eps = 1/64, eta = 0.02, t = 0 -> 1/8 in the mixed
+    precision (swept in FP32 with its near field and refinement) and in the
+    paper-faithful one: energy conserved like the oracle's FP64 run, and
+    the final positions close to it (the runs differ only by rounding over
+    a short interval)."""
+    from oracle import oracle as O
+    from paper_1104_2700_amd import inputs
+    x, v, m = inputs.plummer(1024, 1)
+    eps2 = (1.0 / 64) ** 2
+    tb = 20
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    T_end = 1 << (tb - 3)
+    saved = fp32_policy(H, ctx)
+    try:
+        s = H.State(x, v, m, tb)
+        ctx.initialize(s, eps2, params, H.FP64)
+        e0 = ctx.energy(s, eps2)[0].sum().item()
+        steps, inter = ctx.run(s, eps2, params, T_end, prec, use_graph=True, sync_every=64)
+        e1 = ctx.energy(s, eps2)[0].sum().item()
+    finally:
+        restore_policy(ctx, saved)
+    g = s.to_numpy()
+    assert np.all(g["t"] == T_end)
+    ost = O.new_state(x, v, m, tb)
+    stats = O.run(ost, T_end, eps2, 0.02, 0, 3, 20)
+    K0, W0 = O.energy(x, v, m, eps2)
+    K1, W1 = O.energy(ost["x"], ost["v"], m, eps2)
+    d_gpu = abs(e1 - e0) / abs(e0)
+    d_ora = abs((K1 + W1) - (K0 + W0)) / abs(K0 + W0)
+    assert d_gpu < 1e-6 and d_ora < 1e-6, (d_gpu, d_ora)
+    assert np.abs(g["x"] - ost["x"]).max() < 1e-5
+    # the step sizes follow the FP64 run's (no collapse to the smallest step)
+    assert abs(steps - stats["steps"]) <= 0.05 * stats["steps"], (steps, stats["steps"])
