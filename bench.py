@@ -11,11 +11,17 @@ the active block is all N particles and every step does N^2 interactions
 
 Metric: interactions/s (N_act * N per step) and GFLOPS at the paper's 60
 flops per interaction, for the mixed path (headline) and the FP64 path.
-The roofline entry is for the sweep kernel (the dominant kernel), with its
-average duration measured by HIP events on the launch stream, priced at 42
-algorithmic flops per interaction (count of the operations in the force,
-jerk and potential equations, FMA = 2).  The cpu_baseline entry times the
-FP64 CPU oracle on a bounded sample of active particles of the same state.
+The mixed path runs with the library's default policy: FP64 near field and
+the FP64 refinement of the particles whose FP32 rounding estimate exceeds
+the bound, so that every particle meets 1e-6 (the count refined per step is
+reported).  The roofline entry is for the sweep kernel (the dominant
+kernel), with its average duration measured by HIP events recorded on the
+launch stream around that kernel alone, priced at 42 algorithmic flops per
+interaction (count of the operations in the force, jerk and potential
+equations, FMA = 2); the whole force call (plan, sweep, reduce/refine) is
+reported beside it.  Both FP32 difference forms of the mixed sweep (cast and
+split hi/lo) are timed and checked.  The cpu_baseline entry times the FP64
+CPU oracle on a bounded sample of active particles of the same state.
 """
 from __future__ import annotations
 
@@ -55,6 +61,8 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other FP32 difference form of the mixed sweep")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape")
     ap.add_argument("--tuning-cache", default=os.path.join(tempfile.gettempdir(),
@@ -97,7 +105,6 @@ def main():
     ctx.initialize(base, eps2, params, H.FP64)
     torch.cuda.synchronize()
     h_ticks = 1 << (TB - H_SHARED_K)
-    stream = torch.cuda.current_stream()
 
     results = {}
     precs = [p for p in args.precisions.split(",") if p]
@@ -130,6 +137,7 @@ def main():
         for _ in range(args.warmup):
             one_step()
         torch.cuda.synchronize()
+        c0 = ctx.counters()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             one_step()
@@ -139,29 +147,64 @@ def main():
         assert cnt["n_act"] == N, cnt
         ms_step = 1e3 * wall / args.steps
         inter_s = N * N / (wall / args.steps)
-        # kernel-level timing of the sweep (plan + sweep + reduce) with HIP
-        # events on the launch stream, at the same launch shape
+        refined = (cnt["refined"] - c0["refined"]) / args.steps
+        # kernel-level timing of the force call at the same launch shape: HIP
+        # events on the launch stream around the plan kernel, the sweep
+        # kernel and the finishing kernels (reduce; flag, FP64 refine sweep
+        # and scatter for the refining mixed sweep)
         fs = base.clone()
         fs.xp.copy_(fs.x)
         fs.vp.copy_(fs.v)
-        acc, jrk, pot = ctx.force_jerk(fs, None, eps2, prec)
         reps = max(10, args.steps)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            ctx.force_jerk(fs, None, eps2, prec, acc=acc, jerk=jrk, pot=pot)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        k_ms = e0.elapsed_time(e1) / reps
+        acc, jrk, pot, _ = ctx.force_jerk_timed(fs, None, eps2, prec, reps=2)
+        acc, jrk, pot, ph = ctx.force_jerk_timed(fs, None, eps2, prec, reps=reps,
+                                                 acc=acc, jerk=jrk, pot=pot)
         results[pname] = {
             "ms_per_step": ms_step, "interactions_per_s": inter_s,
             "gflops_60": inter_s * FLOPS_PAPER / 1e9,
-            "sweep_ms": k_ms,
-            "sweep_interactions_per_s": N * N / (k_ms * 1e-3),
+            "refined_per_step": refined,
+            "force_ms": ph,
+            "sweep_kernel_interactions_per_s": N * N / (ph["sweep"] * 1e-3),
+            "force_call_interactions_per_s": N * N / (ph["total"] * 1e-3),
             "tuning": tuning,
             "out": (acc.cpu().numpy(), jrk.cpu().numpy(), pot.cpu().numpy()),
         }
+        if pname in ("mixed", "mixed2f") and not args.no_variants:
+            # the other form of the FP32 differences (cast <-> split hi/lo),
+            # same launch shape otherwise
+            t = ctx.get_tuning(prec)
+            keep = t.variant
+            t.variant = keep ^ 2
+            ctx.set_tuning(prec, t)
+            a2, j2, p2, ph2 = ctx.force_jerk_timed(fs, None, eps2, prec, reps=reps)
+            t.variant = keep
+            ctx.set_tuning(prec, t)
+            form = "split" if (keep ^ 2) & 2 else "cast"
+            results[pname + "_" + form] = {
+                "force_ms": ph2, "tuning": dict(tuning, variant=keep ^ 2),
+                "sweep_kernel_interactions_per_s": N * N / (ph2["sweep"] * 1e-3),
+                "force_call_interactions_per_s": N * N / (ph2["total"] * 1e-3),
+                "out": (a2.cpu().numpy(), j2.cpu().numpy(), p2.cpu().numpy()),
+            }
+        del fs
+
+    # every particle of the mixed outputs against the FP64 sweep of the
+    # same state (the FP64 path is held to the oracle at 1e-13 by the tests)
+    if "fp64" in results:
+        A0, J0, P0 = results["fp64"]["out"]
+        for p, r in results.items():
+            if p == "fp64":
+                continue
+            A, J, P = r["out"]
+            ea = np.linalg.norm(A - A0, axis=0) / np.linalg.norm(A0, axis=0)
+            ej = np.linalg.norm(J - J0, axis=0) / np.linalg.norm(J0, axis=0)
+            ep = np.abs(P - P0) / np.abs(P0)
+            r["all_particles_vs_fp64_sweep"] = {
+                "acc_rel_max": float(ea.max()), "jerk_rel_max": float(ej.max()),
+                "jerk_rel_p999": float(np.percentile(ej, 99.9)),
+                "jerk_n_above_1e-6": int((ej > 1e-6).sum()),
+                "acc_n_above_1e-6": int((ea > 1e-6).sum()),
+                "pot_rel_max": float(ep.max())}
 
     cpu = None
     accuracy = {}
@@ -170,7 +213,8 @@ def main():
 
     head = "mixed" if "mixed" in results else precs[0]
     r = results[head]
-    achieved = FLOPS_ALGO * N * N / (r["sweep_ms"] * 1e-3)
+    sweep_ms = r["force_ms"]["sweep"]
+    achieved = FLOPS_ALGO * N * N / (sweep_ms * 1e-3)
     peak = PEAK_FP32 if head != "fp64" else PEAK_FP64
     prof = profiled_counters()
     traffic = issued = None
@@ -179,7 +223,7 @@ def main():
     if prof is not None and head in prof and prof[head].get("tuning") == r["tuning"]:
         traffic = prof[head]["traffic_bytes"]
         fl = prof[head]["fp32_flops_per_interaction"] + prof[head]["fp64_flops_per_interaction"]
-        issued = fl * N * N / (r["sweep_ms"] * 1e-3) / 1e12
+        issued = fl * N * N / (sweep_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": r["interactions_per_s"],
@@ -202,7 +246,8 @@ def main():
         "accuracy_vs_oracle": accuracy,
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep (plan+sweep+reduce), precision %s" % head,
+            "kernel": "force sweep kernel (hermite_sweep), precision %s, variant %d"
+                      % (head, r["tuning"]["variant"]),
             "achieved": achieved / 1e12,
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
@@ -211,6 +256,9 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "issued_tflops_from_counters": issued,
             "flops_per_interaction": FLOPS_ALGO,
+            "kernel_ms": sweep_ms,
+            "force_call_ms": r["force_ms"]["total"],
+            "force_call_frac": FLOPS_ALGO * N * N / (r["force_ms"]["total"] * 1e-3) / peak,
             "frac_vs_fp64_or_unpacked_fp32_peak": achieved / PEAK_FP64,
         },
         "cpu_baseline": cpu,
@@ -220,8 +268,9 @@ def main():
         out["fp64_vs_mixed"] = {
             "fp64_interactions_per_s": f["interactions_per_s"],
             "mixed_speedup_step": r["interactions_per_s"] / f["interactions_per_s"],
-            "mixed_speedup_sweep": f["sweep_ms"] / r["sweep_ms"],
-            "fp64_sweep_frac_fp64_peak": FLOPS_ALGO * N * N / (f["sweep_ms"] * 1e-3) / PEAK_FP64,
+            "mixed_speedup_force_call": f["force_ms"]["total"] / r["force_ms"]["total"],
+            "fp64_sweep_frac_fp64_peak":
+                FLOPS_ALGO * N * N / (f["force_ms"]["sweep"] * 1e-3) / PEAK_FP64,
         }
     print(json.dumps(out), flush=True)
 

@@ -121,9 +121,11 @@ typedef struct hermite_tuning {
     int32_t target_lanes;     /* lanes the j-split aims to keep busy      */
     int32_t wg_per_cu;        /* persistent workgroups per compute unit   */
     int32_t min_j_per_lane;   /* smallest j-run a lane is given per chunk */
-    int32_t variant;          /* inner loop, 0..3: bit 0 = two active     */
+    int32_t variant;          /* inner loop, 0..7: bit 0 = two active     */
                               /* particles per lane; bit 1 = FP32 hi/lo   */
-                              /* split differences (MIXED, MIXED_2F only) */
+                              /* split differences (MIXED, MIXED_2F only);*/
+                              /* bit 2 = FP32 runs of 32 terms instead of */
+                              /* 16 between FP64 flushes (mixed modes)    */
 } hermite_tuning;
 
 typedef struct hermite_ctx hermite_ctx;
@@ -183,6 +185,21 @@ int hermite_force_jerk(hermite_ctx* ctx, const hermite_state* s,
                        const int32_t* idx, const int32_t* n_act_dev,
                        int32_t n_act_max, double eps2, int precision,
                        double* acc, double* jerk, double* pot, void* stream);
+
+/* Profiling form of hermite_force_jerk (Section 5's per-interaction
+ * speed): the same sweep run reps times over the first n_act entries of idx
+ * (or all particles, idx NULL and n_act == n), each time bracketed by HIP
+ * events on the given stream, waiting for each run to end.  ms_out (host,
+ * 4 doubles) receives the average duration in milliseconds of the plan
+ * kernel, the sweep kernel(s), the finishing kernels (reduction of the
+ * partial sums and, for a refining mixed sweep, the flagging, FP64 refine
+ * sweep and scatter) and the whole call.  Outputs as hermite_force_jerk.
+ * EINVAL for reps < 1 or a bad size; EHIP when an event call fails. */
+int hermite_force_jerk_timed(hermite_ctx* ctx, const hermite_state* s,
+                             const hermite_clusters* cl, const int32_t* idx,
+                             int32_t n_act, double eps2, int precision,
+                             double* acc, double* jerk, double* pot,
+                             int32_t reps, double* ms_out, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
@@ -355,8 +372,9 @@ int hermite_get_mixed_policy(hermite_ctx* ctx, int precision, double* near_facto
 int hermite_set_tuning(hermite_ctx* ctx, int precision,
                        const hermite_tuning* in);
 
-/* Time candidate launch shapes (variant, workgroups per CU, j-split
- * target, minimum j-run) of the sweep for this state (and clusters, may be
+/* Time candidate launch shapes (variant, i.e. particles per lane, FP32
+ * difference form and FP32 run length; workgroups per CU, j-split target,
+ * minimum j-run) of the sweep for this state (and clusters, may be
  * NULL), precision and active count (the first n_act particles) with HIP
  * events at the predicted positions s->xp, s->vp, and keep the fastest
  * whose results stay as close to an FP64 sweep as the precision allows
@@ -364,10 +382,10 @@ int hermite_set_tuning(hermite_ctx* ctx, int precision,
  * deviation, whichever is larger).  Every candidate is screened with a few
  * launches; the six fastest and the default are then timed again in three
  * interleaved rounds, and the lowest median wins.  Installs it in the
- * context and, if
- * cache_path is non-NULL, merges it into that JSON file keyed by device
- * architecture, HIP version, precision and power-of-two size buckets of
- * n and n_act.  Synchronises. */
+ * context and, if cache_path is non-NULL, merges it into that JSON file
+ * keyed by device architecture, HIP version, precision and power-of-two
+ * size buckets of n and n_act, with its time and the HBM bytes its j-split
+ * adds (partial sums written and read back).  Synchronises. */
 int hermite_autotune(hermite_ctx* ctx, const hermite_state* s,
                      const hermite_clusters* cl, double eps2, int precision,
                      int32_t n_act, const char* cache_path, void* stream);

@@ -134,8 +134,11 @@ inline int reduce_grid(int64_t n_act_max)
 // ra (or null): the refine sweep of a mixed sweep with refinement (a.refine):
 // the reduce flags and plans, the FP64 refine sweep runs, and the refined
 // sums are scattered into the outputs.
+// marks (or null): two events recorded on st after the plan kernel and after
+// the sweep kernel(s), so that each phase can be timed on its own stream.
 hipError_t launch_force(const SweepArgs& a, const SweepArgs* ra, int precision, int variant,
-                        int grid, bool pot_only, hipStream_t st);
+                        int grid, bool pot_only, hipStream_t st,
+                        const hipEvent_t* marks = nullptr);
 
 // Block-step form of the refinement: the flagging reduce into the compact
 // outputs a.acc / a.jerk / a.pot, then the FP64 refine sweep (the corrector,
@@ -232,41 +235,42 @@ struct LevelArgs {
     const int64_t* t;
     const int64_t* dt;
     int64_t dt_floor;    // smallest step the corrector can give, 2^(tick_bits - k_max)
-    int32_t* perm;       // [n] particle ids by step size, smallest first
-    int32_t* cnt;        // [64] particles with dt = 2^b ticks
+    int32_t* perm;       // [n] particle ids by step size, smallest first (ensembles:
+                         // within each cluster's range)
+    int32_t* cnt;        // [64] particles with dt = 2^b ticks (one system)
     int32_t* cursor;     // [64] (building the order)
     int64_t* misc;       // [0] T_last; [1] max t, [2] min t + dt, [3] inconsistent (checks);
-                         // [4] a workgroup barrier of the selection timed out
+                         // [4] a position out of range was not written
     int32_t* tmp;        // [n] re-sort scratch for blocks beyond the LDS staging
-    int32_t* wg_hist;    // [kLevelGrid][64] per-workgroup step counts (large blocks)
-    int32_t* wg_chist;   // [kLevelGrid][kLdsClusters] per-workgroup cluster counts
-    uint32_t* bar;       // [4] workgroup barrier: arrivals, generation; [2], [3]
-                         // n_act posted by workgroup 0 and its readers (all
-                         // zeroed once, left zero)
     int32_t* na_prev;    // the previous block's n_act, written by the corrector
-                         // (*na is rewritten by workgroup 0 while the others may
-                         // still be starting)
     uint32_t* bits;      // [(n + 31) / 32] active-particle bitmap (zeroed once, left zero)
     int64_t T_end;
     int32_t* na;         // n_act: the previous step's in, this step's out
     int64_t* T;          // block time: the previous step's in, this step's out
     int32_t* idx;        // [n] active list grouped by cluster (C > 1)
     int64_t* counters;
+    // ensembles (C > 1): per-cluster step-size orders
+    int32_t n_clusters;
+    const int64_t* offsets;  // [C + 1]
+    int32_t* ccnt;       // [C][64] particles of cluster c with dt = 2^b ticks
+    int32_t* ccum;       // [C][64] their running sums over b (steps <= 2^b)
+    int32_t* cmin;       // [C] smallest occupied b of cluster c (64: none)
+    int32_t* cna;        // [C] size of cluster c's last block
 };
 
 // Counts the steps of a state and checks that it is one the block scheme
 // can have produced (misc[1..3]); misc and cnt must hold {0, INT64_MIN,
 // INT64_MAX, 0} and zeros.  launch_level_build then orders the particles
-// (cursor zeroed) and sets T_last = max t and *na = 0.
+// (cursor zeroed; ensembles: per cluster) and sets T_last = max t and
+// *na = *na_prev = 0.
 hipError_t launch_level_count(const LevelArgs& L, hipStream_t st);
 hipError_t launch_level_build(const LevelArgs& L, hipStream_t st);
 // Re-sorts the previous block by its new steps, selects the next block,
-// groups it by cluster (C > 1; C <= kLdsClusters) and plans the sweep.
-// One system takes one workgroup.  With clusters, blocks up to a few
-// thousand particles take workgroup 0; larger ones are shared by
-// kLevelGrid workgroups that meet at barriers (all of them are resident at
-// once: the kernel runs alone on the stream and needs little).
-constexpr int kLevelGrid = 16;
+// lists it (ensembles: grouped by cluster, C <= kLdsClusters) and plans the
+// sweep.  One system: one workgroup.  Ensembles: two kernels, a re-sort
+// with one workgroup per cluster, then the selection, in which every
+// workgroup derives the block from the same tables and lists the blocks of
+// its clusters; no workgroup waits on another.
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st);
 hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipStream_t st);
 

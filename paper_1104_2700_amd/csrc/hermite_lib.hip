@@ -82,7 +82,8 @@ struct hermite_ctx {
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
-    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_wg, lvl_wgc, lvl_bar, lvl_bits;
+    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_na, lvl_bits;
+    Buf lvl_ccnt, lvl_ccum, lvl_cmin, lvl_cna;   // ensembles: per-cluster orders
     std::vector<GraphEntry> graphs;
     // grid of the fused select + sweep for the last shape it was sized for
     struct {
@@ -445,8 +446,8 @@ int ensure_step_scratch(hermite_ctx* c, int64_t n)
     return HERMITE_OK;
 }
 
-LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* p,
-                     int64_t T_end)
+LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                     const hermite_dt_params* p, int64_t T_end)
 {
     LevelArgs L;
     std::memset(&L, 0, sizeof L);
@@ -459,24 +460,30 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_dt_pa
     L.cursor = (int32_t*)c->lvl_cursor.p;
     L.misc = (int64_t*)c->lvl_misc.p;
     L.tmp = (int32_t*)c->lvl_tmp.p;
-    L.wg_hist = (int32_t*)c->lvl_wg.p;
-    L.wg_chist = (int32_t*)c->lvl_wgc.p;
-    L.bar = (uint32_t*)c->lvl_bar.p;
-    L.na_prev = (int32_t*)c->lvl_bar.p + 4;
+    L.na_prev = (int32_t*)c->lvl_na.p;
     L.bits = (uint32_t*)c->lvl_bits.p;
     L.T_end = T_end;
     L.na = (int32_t*)c->step_na.p;
     L.T = (int64_t*)c->step_T.p;
     L.idx = (int32_t*)c->step_idx.p;
     L.counters = (int64_t*)c->counters.p;
+    L.n_clusters = cl ? cl->n_clusters : 1;
+    if (cl && cl->n_clusters > 1) {
+        L.offsets = cl->offsets;
+        L.ccnt = (int32_t*)c->lvl_ccnt.p;
+        L.ccum = (int32_t*)c->lvl_ccum.p;
+        L.cmin = (int32_t*)c->lvl_cmin.p;
+        L.cna = (int32_t*)c->lvl_cna.p;
+    }
     return L;
 }
 
-// Builds the step-size order of s for a run (synchronises st).  *ok is
-// false when the state is not one the block scheme can have produced (the
-// run then selects every block from t and dt).
-int level_init(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* p,
-               hipStream_t st, bool* ok)
+// Builds the step-size order of s for a run (per cluster for ensembles;
+// synchronises st).  *ok is false when the state is not one the block
+// scheme can have produced (the run then selects every block from t and
+// dt).
+int level_init(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+               const hermite_dt_params* p, hipStream_t st, bool* ok)
 {
     *ok = false;
     CHECK(ensure(c, c->lvl_perm, sizeof(int32_t) * s->n));
@@ -484,16 +491,21 @@ int level_init(hermite_ctx* c, const hermite_state* s, const hermite_dt_params* 
     CHECK(ensure(c, c->lvl_cnt, sizeof(int32_t) * 64));
     CHECK(ensure(c, c->lvl_cursor, sizeof(int32_t) * 64));
     CHECK(ensure(c, c->lvl_misc, sizeof(int64_t) * 8));
-    CHECK(ensure(c, c->lvl_wg, sizeof(int32_t) * kLevelGrid * 64));
-    CHECK(ensure(c, c->lvl_wgc, sizeof(int32_t) * kLevelGrid * kLdsClusters));
-    CHECK(ensure(c, c->lvl_bar, sizeof(uint32_t) * 8));
+    CHECK(ensure(c, c->lvl_na, sizeof(int32_t) * 2));
     CHECK(ensure(c, c->lvl_bits, sizeof(uint32_t) * ((s->n + 31) / 32)));
-    const LevelArgs L = level_args(c, s, p, 0);
+    if (cl && cl->n_clusters > 1) {
+        const size_t C = (size_t)cl->n_clusters;
+        CHECK(ensure(c, c->lvl_ccnt, sizeof(int32_t) * 64 * C));
+        CHECK(ensure(c, c->lvl_ccum, sizeof(int32_t) * 64 * C));
+        CHECK(ensure(c, c->lvl_cmin, sizeof(int32_t) * C));
+        CHECK(ensure(c, c->lvl_cna, sizeof(int32_t) * C));
+    }
+    const LevelArgs L = level_args(c, s, cl, p, 0);
     const int64_t init[8] = {0, INT64_MIN, INT64_MAX, 0, 0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(L.misc, init, sizeof init, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * 64, st));
     HIP_OK(hipMemsetAsync(L.cursor, 0, sizeof(int32_t) * 64, st));
-    HIP_OK(hipMemsetAsync(L.bar, 0, sizeof(uint32_t) * 8, st));
+    HIP_OK(hipMemsetAsync(L.na_prev, 0, sizeof(int32_t) * 2, st));
     HIP_OK(hipMemsetAsync(L.bits, 0, sizeof(uint32_t) * ((s->n + 31) / 32), st));
     // every entry of the active list and its clusters holds a valid index
     // from the start, whatever a step writes
@@ -546,7 +558,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     a.tick = std::ldexp(1.0, -s->tick_bits);
     const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
     if (level) {
-        HIP_OK(launch_level_select(level_args(c, s, p, T_end), a, st));
+        HIP_OK(launch_level_select(level_args(c, s, cl, p, T_end), a, st));
         HIP_OK(launch_sweep_only(a, precision, tu.variant, grid, st));
     } else if (!cl && n <= kFusedSelMax) {
         // one small system: every sweep workgroup selects the block itself
@@ -597,7 +609,7 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.k_max = p->k_max;
     ca.counters = counters;
     ca.predict_i = 1;
-    if (level) ca.na_seen = (int32_t*)c->lvl_bar.p + 4;
+    if (level) ca.na_seen = (int32_t*)c->lvl_na.p;
     if (a.refine) {
         // mixed sums into the compact outputs with their error flags, the
         // FP64 refine sweep of the flagged particles, then the corrector
@@ -794,7 +806,8 @@ int hermite_destroy(hermite_ctx* c)
                    &c->rpartial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
                    &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
-                   &c->lvl_cursor, &c->lvl_misc, &c->lvl_wg, &c->lvl_wgc, &c->lvl_bar,
+                   &c->lvl_cursor, &c->lvl_misc, &c->lvl_na, &c->lvl_ccnt, &c->lvl_ccum,
+                   &c->lvl_cmin, &c->lvl_cna,
                    &c->lvl_bits};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -857,6 +870,59 @@ int hermite_force_jerk(hermite_ctx* c, const hermite_state* s, const hermite_clu
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, precision, tu, acc,
                         jerk, pot, &a));
     return run_force(c, a, precision, tu, false, (hipStream_t)stream);
+}
+
+int hermite_force_jerk_timed(hermite_ctx* c, const hermite_state* s, const hermite_clusters* cl,
+                             const int32_t* idx, int32_t n_act, double eps2, int precision,
+                             double* acc, double* jerk, double* pot, int32_t reps,
+                             double* ms_out, void* stream)
+{
+    CHECK(check_ctx(c));
+    CHECK(check_state(s));
+    CHECK(check_precision(precision));
+    CHECK(check_clusters(cl, s->n));
+    if (!cl) CHECK(check_eps2(eps2));
+    if (n_act < 1 || n_act > s->n) return fail(HERMITE_EINVAL, "n_act = %d out of range [1, n]", n_act);
+    if (!idx && n_act != s->n)
+        return fail(HERMITE_EINVAL, "identity index list needs n_act == n");
+    if (!acc || !jerk || !ms_out) return fail(HERMITE_EINVAL, "null output pointer");
+    if (reps < 1) return fail(HERMITE_EINVAL, "reps = %d < 1", reps);
+    hipStream_t st = (hipStream_t)stream;
+    SweepArgs a;
+    const hermite_tuning& tu = c->tuning[precision];
+    CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, idx, nullptr, n_act, eps2, precision, tu, acc,
+                        jerk, pot, &a));
+    SweepArgs ra;
+    if (a.refine) CHECK(prepare_refine(c, a, &ra));
+    const int grid = std::max(1, c->n_cu * tu.wg_per_cu);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int rc = HERMITE_OK;
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < 4 && rc == HERMITE_OK; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) rc = fail(HERMITE_EHIP, "hipEventCreate failed");
+    for (int r = 0; r < reps && rc == HERMITE_OK; ++r) {
+        hipError_t e = hipEventRecord(ev[0], st);
+        if (e == hipSuccess)
+            e = launch_force(a, a.refine ? &ra : nullptr, precision, tu.variant, grid, false, st,
+                             ev + 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        float ms[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
+        if (e != hipSuccess) {
+            rc = fail(HERMITE_EHIP, "timed sweep: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int k = 0; k < 3; ++k) {
+            sum[k] += ms[k];
+            sum[3] += ms[k];
+        }
+    }
+    for (int k = 0; k < 4; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    CHECK(rc);
+    for (int k = 0; k < 4; ++k) ms_out[k] = sum[k] / reps;
+    return HERMITE_OK;
 }
 
 int hermite_force_jerk_noalloc(const hermite_state* s, const hermite_clusters* cl,
@@ -1147,7 +1213,7 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
     if (!(cl == nullptr && s->n <= kFusedSelMax) && (!cl || cl->n_clusters <= kLdsClusters)) {
         CHECK(check_clusters(cl, s->n));
         CHECK(ensure_step_scratch(c, s->n));
-        CHECK(level_init(c, s, p, st, &level));
+        CHECK(level_init(c, s, cl, p, st, &level));
     }
     int64_t launched = 0;
     int32_t done = 0;
@@ -1166,16 +1232,13 @@ int hermite_run(hermite_ctx* c, const hermite_state* s, const hermite_clusters* 
         int32_t na = 0;
         HIP_OK(hipMemcpyAsync(&T, c->step_T.p, sizeof T, hipMemcpyDeviceToHost, st));
         HIP_OK(hipMemcpyAsync(&na, c->step_na.p, sizeof na, hipMemcpyDeviceToHost, st));
-        int64_t timeout = 0;
+        int64_t inconsistent = 0;
         if (level)
-            HIP_OK(hipMemcpyAsync(&timeout, (int64_t*)c->lvl_misc.p + 4, sizeof timeout,
-                                  hipMemcpyDeviceToHost, st));
+            HIP_OK(hipMemcpyAsync(&inconsistent, (int64_t*)c->lvl_misc.p + 4,
+                                  sizeof inconsistent, hipMemcpyDeviceToHost, st));
         int bad = 0;
         CHECK(check_finite(c, s, st, &bad));   // synchronises st
-        if (timeout == 1)
-            return fail(HERMITE_EHIP, "block selection: a workgroup barrier timed out "
-                        "(workgroups not resident together)");
-        if (timeout)
+        if (inconsistent)
             return fail(HERMITE_EHIP, "block selection: inconsistent step-size order "
                         "(a position out of range was not written)");
         if (bad)
@@ -1237,7 +1300,7 @@ int hermite_set_tuning(hermite_ctx* c, int precision, const hermite_tuning* in)
     if (!c || !in) return fail(HERMITE_EINVAL, "null argument");
     CHECK(check_precision(precision));
     if (in->wg_per_cu < 1 || in->wg_per_cu > 64 || in->target_lanes < kWG ||
-        in->min_j_per_lane < 1 || in->variant < 0 || in->variant > 3)
+        in->min_j_per_lane < 1 || in->variant < 0 || in->variant > 7)
         return fail(HERMITE_EINVAL, "tuning out of range");
     c->tuning[precision] = *in;
     return HERMITE_OK;
@@ -1272,7 +1335,10 @@ std::string cache_key(const hermite_ctx* c, int precision, int64_t n, int32_t n_
 }
 
 // The cache is a JSON object with one entry per line:
-//   "key": {"target_lanes": T, "wg_per_cu": W, "min_j_per_lane": M, "variant": V, "us": U},
+//   "key": {"target_lanes": T, "wg_per_cu": W, "min_j_per_lane": M, "variant": V, "us": U,
+//           "partial_bytes": B},
+// (U: the sweep's median time in microseconds; B: HBM bytes of its j-split
+// partial sums, written and read back).
 std::map<std::string, std::string> read_cache(const char* path)
 {
     std::map<std::string, std::string> m;
@@ -1394,7 +1460,7 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
         e[2] = max_rel_diff(g, r, n_act, 6, 7);
     };
     int rc = HERMITE_OK;
-    double best_us = 0.0;
+    double best_us = 0.0, partial_bytes = 0.0;
     hermite_tuning best = base;
     std::vector<std::pair<double, hermite_tuning>> passed;   // screened candidates
     const double tol = precision == HERMITE_FP64 ? 1e-13 : 1e-6;
@@ -1412,8 +1478,17 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
         for (int q = 0; q < 3; ++q) limit[q] = std::max(tol, 1.5 * e[q]);
         const std::vector<int> mjs = n_act >= 8192 ? std::vector<int>{4}
                                                    : std::vector<int>{4, 16, 64};
-        const int nvar = (precision == HERMITE_FP64 || precision == HERMITE_MIXED_SP) ? 2 : 4;
-        for (int var = 0; var < nvar && rc == HERMITE_OK; ++var) {
+        // variants: particles per lane (bit 0), FP32 difference form (bit 1,
+        // MIXED and MIXED_2F), FP32 run length (bit 2, mixed precisions)
+        std::vector<int> vars;
+        for (int var = 0; var < 8; ++var) {
+            if ((var & 2) && precision != HERMITE_MIXED && precision != HERMITE_MIXED_2F)
+                continue;
+            if ((var & 4) && precision == HERMITE_FP64) continue;
+            vars.push_back(var);
+        }
+        for (int var : vars) {
+            if (rc != HERMITE_OK) break;
             for (int w = 2; w <= 8 && rc == HERMITE_OK; ++w) {
                 for (int f : {1, 2, 4, 8}) {
                     for (int mj : mjs) {
@@ -1461,6 +1536,17 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
                 best = passed[k].second;
             }
         }
+        // the chosen shape's j-split: its partial sums are written to HBM and
+        // read back by the reduction (one row set per active particle and
+        // j-chunk)
+        rc = run(best, 1, &us, nullptr);
+        if (rc != HERMITE_OK) break;
+        SweepPlan P;
+        if (hipMemcpy(&P, c->plan.p, sizeof P, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = fail(HERMITE_EHIP, "reading the sweep plan failed");
+            break;
+        }
+        partial_bytes = 2.0 * (double)P.s_max * kRows * sizeof(double) * (double)P.n_act;
     } while (0);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1472,7 +1558,8 @@ int hermite_autotune(hermite_ctx* c, const hermite_state* s, const hermite_clust
         std::ostringstream o;
         o << "{\"target_lanes\": " << best.target_lanes << ", \"wg_per_cu\": " << best.wg_per_cu
           << ", \"min_j_per_lane\": " << best.min_j_per_lane << ", \"variant\": "
-          << best.variant << ", \"us\": " << best_us << "}";
+          << best.variant << ", \"us\": " << best_us << ", \"partial_bytes\": "
+          << partial_bytes << "}";
         m[cache_key(c, precision, s->n, n_act)] = o.str();
         CHECK(write_cache(cache_path, m));
     }

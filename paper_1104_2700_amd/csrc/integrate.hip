@@ -462,29 +462,28 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
     }
 }
 
-constexpr int kLevelLds = 2048;   // blocks handled by one workgroup, staged in LDS
+constexpr int kLevelLds = 2048;   // blocks re-sorted in LDS
 constexpr int kLevelBatch = 8;    // elements per thread whose loads are issued together
 constexpr int kLevelOrder = 4096; // one system: blocks listed in particle order
+constexpr int kSelectGrid = 256;  // ensembles: workgroups of the selection
 
-// Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of the
-// order (positions below `split` from the re-sort scratch L.tmp, the rest
-// from L.perm) and, with_steps, their step sizes: every load is issued
+// Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of
+// src[0, cnt) and, with_steps, their step sizes: every load is issued
 // before any is used (addresses clamped to the last position, so none is
 // conditional).
-__device__ __forceinline__ void level_batch(const LevelArgs& L, int32_t cnt, int32_t p0,
-                                            int32_t (&id)[kLevelBatch], int (&b)[kLevelBatch],
-                                            bool with_steps, int32_t split = 0)
+__device__ __forceinline__ void level_batch(const int32_t* src, const int64_t* dt, int32_t cnt,
+                                            int32_t p0, int32_t (&id)[kLevelBatch],
+                                            int (&b)[kLevelBatch], bool with_steps)
 {
 #pragma unroll
     for (int u = 0; u < kLevelBatch; ++u) {
         const int32_t p = p0 + u * kWG + (int32_t)threadIdx.x;
-        const int32_t pc = p < cnt ? p : cnt - 1;
-        id[u] = (pc < split ? L.tmp : L.perm)[pc];
+        id[u] = src[p < cnt ? p : cnt - 1];
     }
     if (with_steps) {
         int64_t d[kLevelBatch];
 #pragma unroll
-        for (int u = 0; u < kLevelBatch; ++u) d[u] = L.dt[id[u]];
+        for (int u = 0; u < kLevelBatch; ++u) d[u] = dt[id[u]];
 #pragma unroll
         for (int u = 0; u < kLevelBatch; ++u) b[u] = log2_step(d[u]);
     }
@@ -503,367 +502,174 @@ __device__ __forceinline__ bool level_put(const LevelArgs& L, int32_t* out, int3
     return false;
 }
 
-// Barrier of all workgroups of the selection (every one calls it at the
-// same points).  The wait is bounded: past the limit it records the
-// timeout in misc[4] and goes on, so the kernel always ends.
-__device__ void level_barrier(const LevelArgs& L)
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int32_t wave_inscan_i32(int32_t x)
 {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    return x;
+}
+
+struct LevelLds {
+    int32_t hist[64], cur[64], cnt[64];
+    int32_t id[kLevelLds];
+    int32_t aux[kLevelLds];
+    uint8_t lv[kLevelLds];
+};
+
+// Re-sorts the last block, perm[0, m), by the steps the corrector gave it
+// (a counting sort by step size; staged in LDS up to kLevelLds, else
+// through tmp[0, m)).  Every particle of that block had a step dividing
+// the block time 2^z * odd and got a new one that divides it, and every
+// particle after it has a larger step, so the whole order stays sorted.
+// S.cnt (the order's step counts) gets the block's counts for steps <= 2^z.
+// All threads of the workgroup call it; it ends with a barrier.
+__device__ void level_resort(const LevelArgs& L, int32_t* perm, int32_t* tmp, int32_t m, int z,
+                             LevelLds& S)
+{
+    const int tid = threadIdx.x;
+    constexpr int kStride = kWG * kLevelBatch;
+    const bool lds = m <= kLevelLds;
+    if (tid < 64) S.hist[tid] = 0;
     __syncthreads();
-    if (gridDim.x > 1 && threadIdx.x == 0) {
-        uint32_t* count = L.bar;
-        uint32_t* gen = L.bar + 1;
-        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived =
-            __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int64_t spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (++spins > (int64_t(1) << 22)) {
-                    __hip_atomic_store(&L.misc[4], (int64_t)1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+    for (int32_t p0 = 0; p0 < m; p0 += kStride) {
+        int32_t id[kLevelBatch];
+        int b[kLevelBatch];
+        level_batch(perm, L.dt, m, p0, id, b, true);
+#pragma unroll
+        for (int u = 0; u < kLevelBatch; ++u) {
+            const int32_t p = p0 + u * kWG + tid;
+            if (p < m) {
+                if (lds) {
+                    S.id[p] = id[u];
+                    S.lv[p] = (uint8_t)b[u];
                 }
-                __builtin_amdgcn_s_sleep(1);
+                atomicAdd(&S.hist[b[u]], 1);
             }
         }
-        __threadfence();
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int32_t hb = S.hist[tid];
+        S.cnt[tid] = (tid <= z ? 0 : S.cnt[tid]) + hb;
+        S.cur[tid] = wave_inscan_i32(hb) - hb;
+    }
+    __syncthreads();
+    if (lds) {
+        for (int32_t p = tid; p < m; p += kWG)
+            level_put(L, S.aux, atomicAdd(&S.cur[S.lv[p]], 1), m, S.id[p]);
+        __syncthreads();
+        for (int32_t p = tid; p < m; p += kWG) perm[p] = S.aux[p];
+    } else {
+        for (int32_t p0 = 0; p0 < m; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(perm, L.dt, m, p0, id, b, true);
+#pragma unroll
+            for (int u = 0; u < kLevelBatch; ++u)
+                if (p0 + u * kWG + tid < m)
+                    level_put(L, tmp, atomicAdd(&S.cur[b[u]], 1), m, id[u]);
+        }
+        __syncthreads();
+        for (int32_t p0 = 0; p0 < m; p0 += kStride) {
+            int32_t id[kLevelBatch];
+            int b[kLevelBatch];
+            level_batch(tmp, L.dt, m, p0, id, b, false);
+#pragma unroll
+            for (int u = 0; u < kLevelBatch; ++u) {
+                const int32_t p = p0 + u * kWG + tid;
+                if (p < m) perm[p] = id[u];
+            }
+        }
     }
     __syncthreads();
 }
 
+// The next block from the step counts (one lane per step size b, lanes of
+// one wave): every particle's next time is the first multiple of its step
+// after T_last, so the block time is the first multiple of the smallest
+// occupied step, and the block is every particle whose step divides it.
+// Returns the block time; *na its size (0 past T_end).
+__device__ __forceinline__ int64_t level_next(int32_t cnt_b, int64_t Tlast, int64_t T_end,
+                                              int32_t* na)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long occ = __ballot(cnt_b > 0);
+    int64_t Tn = INT64_MAX;
+    int32_t v = 0;
+    if (occ != 0ull) {
+        const int bmin = __builtin_ctzll(occ);
+        Tn = ((Tlast >> bmin) + 1) << bmin;
+        const int zn = __builtin_ctzll((unsigned long long)Tn);
+        v = lane <= zn ? cnt_b : 0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    }
+    *na = Tn > T_end ? 0 : v;
+    return Tn;
+}
+
+// One system, one workgroup: the previous block re-sorted, the next block
+// taken as the order's prefix (blocks above kLevelOrder are rewritten in
+// ascending particle order, so that a wave's particles lie close together
+// and fewer j-tiles need the self-pair mask), and the sweep planned.
 __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArgs sa)
 {
-    __shared__ int32_t s_hist[64], s_cur[64], s_cnt[64];
-    __shared__ int32_t s_id[kLevelLds];
-    __shared__ int32_t s_aux[kLevelLds];
-    __shared__ uint8_t s_lv[kLevelLds];
+    __shared__ LevelLds S;
     __shared__ int32_t s_scan[kWG / 64];
     __shared__ int32_t s_na;
-    __shared__ int64_t s_off[kLdsClusters + 1];
-    __shared__ int32_t s_ch[kLdsClusters];
     const int tid = threadIdx.x;
-    const int G = gridDim.x, g = blockIdx.x;
-    const int C = sa.n_clusters;
     const int32_t na_prev = *L.na_prev;
-    const int64_t T_prev = *L.T;
     int64_t Tlast = L.misc[0];
-    const bool r_big = na_prev > kLevelLds;
-    // One system is launched as one workgroup; were it given more, they
-    // would have nothing to do after a small block (nothing is posted for
-    // them to wait on).
-    if (g > 0 && C == 1 && !r_big) return;
-    if (tid < 64) {
-        s_hist[tid] = 0;
-        s_cnt[tid] = L.cnt[tid];
-    }
-    __syncthreads();
-    constexpr int kStride = kWG * kLevelBatch;
-
-    // 1. the previous block, ordered by the steps the corrector gave it
-    // (every particle whose step divides T_prev was in that block): by
-    // workgroup 0 alone when it is small, by all workgroups when large
-    if (na_prev > 0 && (r_big || g == 0)) {
-        Tlast = T_prev;
-        const int z = __builtin_ctzll((unsigned long long)T_prev);
-        if (!r_big) {
-            for (int32_t p0 = 0; p0 < na_prev; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, na_prev, p0, id, b, true);
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    if (p < na_prev) {
-                        s_id[p] = id[u];
-                        s_lv[p] = (uint8_t)b[u];
-                        atomicAdd(&s_hist[b[u]], 1);
-                    }
-                }
-            }
-            __syncthreads();
-            if (tid < 64) {
-                const int32_t hb = s_hist[tid];
-                s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + hb;
-                int32_t x = hb;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int32_t u = __shfl_up(x, o);
-                    if (tid >= o) x += u;
-                }
-                s_cur[tid] = x - hb;
-            }
-            __syncthreads();
-            for (int32_t p = tid; p < na_prev; p += kWG)
-                level_put(L, s_aux, atomicAdd(&s_cur[s_lv[p]], 1), na_prev, s_id[p]);
-            __syncthreads();
-            for (int32_t p = tid; p < na_prev; p += kWG) L.perm[p] = s_aux[p];
-        } else {
-            // shared by all workgroups: per-slice counts, the order of
-            // (step size, workgroup), scatter, copy back
-            const int32_t per = (na_prev + G - 1) / G;
-            const int32_t q0 = g * per < na_prev ? g * per : na_prev;
-            const int32_t q1 = q0 + per < na_prev ? q0 + per : na_prev;
-            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, q1, p0, id, b, true);
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u)
-                    if (p0 + u * kWG + tid < q1) atomicAdd(&s_hist[b[u]], 1);
-            }
-            __syncthreads();
-            if (tid < 64) L.wg_hist[g * 64 + tid] = s_hist[tid];
-            level_barrier(L);
-            if (tid < 64) {
-                int32_t total = 0, before = 0;
-                for (int w = 0; w < G; ++w) {
-                    const int32_t v = L.wg_hist[w * 64 + tid];
-                    total += v;
-                    before += w < g ? v : 0;
-                }
-                s_cnt[tid] = (tid <= z ? 0 : s_cnt[tid]) + total;
-                int32_t x = total;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int32_t u = __shfl_up(x, o);
-                    if (tid >= o) x += u;
-                }
-                s_cur[tid] = x - total + before;
-            }
-            __syncthreads();
-            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, q1, p0, id, b, true);
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u)
-                    if (p0 + u * kWG + tid < q1)
-                        level_put(L, L.tmp, atomicAdd(&s_cur[b[u]], 1), na_prev, id[u]);
-            }
-            level_barrier(L);
-            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-                int32_t v[kLevelBatch];
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    v[u] = L.tmp[p < q1 ? p : q1 - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    if (p < q1) L.perm[p] = v[u];
-                }
-            }
-        }
-        if (g == 0) {
-            if (tid < 64) L.cnt[tid] = s_cnt[tid];
-            if (tid == 0) L.misc[0] = Tlast;
-        }
+    if (tid < 64) S.cnt[tid] = L.cnt[tid];
+    if (na_prev > 0) {
+        Tlast = *L.T;
+        level_resort(L, L.perm, L.tmp, na_prev, __builtin_ctzll((unsigned long long)Tlast), S);
+        if (tid < 64) L.cnt[tid] = S.cnt[tid];
+        if (tid == 0) L.misc[0] = Tlast;
+    } else {
         __syncthreads();
     }
-
-    // 2. next block time and active count (wave 0, one lane per step
-    // size).  After a small block only workgroup 0 knows them; with
-    // clusters it posts n_act + 1 in bar[3], the others take it from there,
-    // and the last of them to do so clears bar[3] and the count bar[2] for
-    // the next call.
-    if (r_big || g == 0) {
-        if (tid < 64) {
-            const int32_t cz = s_cnt[tid];
-            const unsigned long long occ = __ballot(cz > 0);
-            int64_t Tn = INT64_MAX;
-            int32_t na = 0;
-            if (occ != 0ull) {
-                const int bmin = __builtin_ctzll(occ);
-                Tn = ((Tlast >> bmin) + 1) << bmin;
-                const int zn = __builtin_ctzll((unsigned long long)Tn);
-                int32_t v = tid <= zn ? cz : 0;
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                na = v;
-            }
-            if (Tn > L.T_end) na = 0;
-            if (tid == 0) {
-                s_na = na;
-                if (g == 0) {
-                    *L.T = Tn;
-                    *L.na = na;
-                    count_step(L.counters, Tn, na);
-                    if (!r_big && C > 1)
-                        __hip_atomic_store(&L.bar[3], (uint32_t)na + 1u, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-        }
-    } else if (tid == 0) {
-        int64_t spins = 0;
-        uint32_t f;
-        while ((f = __hip_atomic_load(&L.bar[3], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) ==
-               0u) {
-            if (++spins > (int64_t(1) << 22)) {
-                __hip_atomic_store(&L.misc[4], (int64_t)1, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                f = 1u;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        s_na = (int32_t)(f - 1u);
-        if (__hip_atomic_fetch_add(&L.bar[2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-            gridDim.x - 2) {
-            __hip_atomic_store(&L.bar[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&L.bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < 64) {
+        int32_t na;
+        const int64_t Tn = level_next(S.cnt[tid], Tlast, L.T_end, &na);
+        if (tid == 0) {
+            s_na = na;
+            *L.T = Tn;
+            *L.na = na;
+            count_step(L.counters, Tn, na);
         }
     }
     __syncthreads();
     const int32_t na = s_na;
-    // Workgroups that take part in listing the block (0: workgroup 0, and
-    // one system uses the order's prefix as it is).  With clusters the block
-    // is grouped by cluster, by all workgroups when large.  One system (one
-    // workgroup) lists a block above kLevelOrder in ascending particle
-    // order: a wave's particles then lie close together and fewer j-tiles
-    // need the self-pair mask.
-    int parts = 0;
-    if (C == 1)
-        parts = na > kLevelOrder ? G : 0;
-    else
-        parts = na > kLevelLds ? G : 0;
-    if (na == 0) {
-        if (g == 0) plan_body(sa, na);
-        return;
-    }
-    if (g > 0 && parts < G) return;   // workgroup 0 alone from here
-    if (C == 1 && parts == 0) {
+    if (na <= kLevelOrder) {
         plan_body(sa, na);
         return;
     }
-    const bool shared = parts == G;
-    const int gp = shared ? g : 0;
-    // After a shared re-sort the block's first na_prev positions are read
-    // from the scratch (complete since the last barrier; the copy back to
-    // perm may still be under way).  A re-sort by workgroup 0 alone must be
-    // complete before the others read it.
-    const int32_t split = r_big ? na_prev : 0;
-    if (shared && !r_big) level_barrier(L);
-    const int nparts = parts > 0 ? parts : 1;
-    const int32_t per = (na + nparts - 1) / nparts;
-    const int32_t q0 = gp * per < na ? gp * per : na;
-    const int32_t q1 = q0 + per < na ? q0 + per : na;
-
-    if (C > 1) {
-        // 3. the block grouped by cluster (counting sort), with every
-        // cluster's first position and every position's cluster.  Small
-        // blocks are staged in LDS (na <= kLevelLds).
-        for (int k = tid; k <= C; k += kWG) s_off[k] = sa.offsets[k];
-        for (int k = tid; k < C; k += kWG) s_ch[k] = 0;
-        __syncthreads();
-        for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-            int32_t id[kLevelBatch];
-            int b[kLevelBatch];
-            level_batch(L, q1, p0, id, b, false, split);
-#pragma unroll
-            for (int u = 0; u < kLevelBatch; ++u) {
-                const int32_t p = p0 + u * kWG + tid;
-                if (p < q1) {
-                    const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                    if (!shared) {
-                        s_id[p] = id[u];
-                        s_aux[p] = c;
-                    }
-                    atomicAdd(&s_ch[c], 1);
-                }
-            }
-        }
-        __syncthreads();
-        // thread t owns clusters [c0, c1): their totals, this workgroup's
-        // offset within each, and the clusters' first positions
-        const int cper = (C + kWG - 1) / kWG;
-        const int c0 = tid * cper < C ? tid * cper : C;
-        const int c1 = c0 + cper < C ? c0 + cper : C;
-        if (shared) {
-            for (int c = c0; c < c1; ++c) L.wg_chist[g * kLdsClusters + c] = s_ch[c];
-            level_barrier(L);
-            for (int c = c0; c < c1; ++c) {
-                int32_t total = 0, before = 0;
-                for (int w = 0; w < G; ++w) {
-                    const int32_t v = L.wg_chist[w * kLdsClusters + c];
-                    total += v;
-                    before += w < g ? v : 0;
-                }
-                s_ch[c] = total;
-                s_aux[c] = before;
-            }
-            __syncthreads();
-        }
-        int32_t loc = 0;
-        for (int c = c0; c < c1; ++c) loc += s_ch[c];
-        int32_t tot;
-        int32_t run = block_exscan_i32(loc, s_scan, &tot);
-        for (int c = c0; c < c1; ++c) {
-            const int32_t k = s_ch[c];
-            s_ch[c] = run + (shared ? s_aux[c] : 0);
-            if (g == 0) sa.act_start[c] = run;
-            run += k;
-        }
-        __syncthreads();
-        if (!shared) {
-            for (int32_t p = tid; p < na; p += kWG) {
-                const int c = s_aux[p];
-                const int32_t pos = atomicAdd(&s_ch[c], 1);
-                if (level_put(L, L.idx, pos, na, s_id[p])) sa.act_cluster[pos] = c;
-            }
-        } else {
-            for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
-                int32_t id[kLevelBatch];
-                int b[kLevelBatch];
-                level_batch(L, q1, p0, id, b, false, split);
-#pragma unroll
-                for (int u = 0; u < kLevelBatch; ++u) {
-                    const int32_t p = p0 + u * kWG + tid;
-                    if (p < q1) {
-                        const int c = upper_bound_i64(s_off, C + 1, (int64_t)id[u]) - 1;
-                        const int32_t pos = atomicAdd(&s_ch[c], 1);
-                        if (level_put(L, L.idx, pos, na, id[u])) sa.act_cluster[pos] = c;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (g == 0) plan_body(sa, na);   // reads only workgroup 0's act_start
-        return;
-    }
-
-    // 3. one system, a large block: ascending particle order through a
-    // bitmap of the active particles, written over the prefix of the order
-    // (its order within the prefix is free: the next re-sort reorders it)
-    for (int32_t p0 = q0; p0 < q1; p0 += kStride) {
+    // a large block: ascending particle order through a bitmap of the active
+    // particles, written over the prefix of the order (its order within the
+    // prefix is free: the next re-sort reorders it)
+    constexpr int kStride = kWG * kLevelBatch;
+    for (int32_t p0 = 0; p0 < na; p0 += kStride) {
         int32_t id[kLevelBatch];
         int b[kLevelBatch];
-        level_batch(L, q1, p0, id, b, false, split);
+        level_batch(L.perm, L.dt, na, p0, id, b, false);
 #pragma unroll
         for (int u = 0; u < kLevelBatch; ++u)
-            if (p0 + u * kWG + tid < q1) atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
+            if (p0 + u * kWG + tid < na) atomicOr(&L.bits[id[u] >> 5], 1u << (id[u] & 31));
     }
-    if (shared) level_barrier(L);
-    else __syncthreads();
-    // this workgroup owns words [w0, w1) of the bitmap, thread t a
-    // contiguous run [wa, wb) of them
+    __syncthreads();
+    // thread t owns a contiguous run [wa, wb) of the bitmap's words
     const int64_t nw = (L.n + 31) >> 5;
-    const int64_t wper = (nw + nparts - 1) / nparts;
-    const int64_t w0 = (int64_t)gp * wper < nw ? (int64_t)gp * wper : nw;
-    const int64_t w1 = w0 + wper < nw ? w0 + wper : nw;
-    const int64_t tper = (w1 - w0 + kWG - 1) / kWG;
-    const int64_t wa = w0 + tid * tper < w1 ? w0 + tid * tper : w1;
-    const int64_t wb = wa + tper < w1 ? wa + tper : w1;
+    const int64_t tper = (nw + kWG - 1) / kWG;
+    const int64_t wa = tid * tper < nw ? tid * tper : nw;
+    const int64_t wb = wa + tper < nw ? wa + tper : nw;
     int32_t cnt = 0;
     for (int64_t w = wa; w < wb; ++w) cnt += __popc(L.bits[w]);
-    int32_t wg_total;
-    int32_t pos = block_exscan_i32(cnt, s_scan, &wg_total);
-    if (shared) {
-        if (tid == 0) L.wg_hist[g * 64] = wg_total;
-        level_barrier(L);
-        for (int w = 0; w < g; ++w) pos += L.wg_hist[w * 64];
-    }
+    int32_t total;
+    int32_t pos = block_exscan_i32(cnt, s_scan, &total);
     for (int64_t w = wa; w < wb; ++w) {
         uint32_t word = L.bits[w];
         L.bits[w] = 0u;
@@ -872,7 +678,140 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
             word &= word - 1u;
         }
     }
-    if (g == 0) plan_body(sa, na);
+    __syncthreads();
+    plan_body(sa, na);
+}
+
+// Ensembles.  Cluster c keeps its own step-size order in its range of perm,
+// perm[off_c, off_c+1), with its step counts ccnt[c][b], their running sums
+// ccum[c][b] and its smallest occupied step cmin[c]; all clusters share the
+// block time, and cluster c's part of a block is a prefix of its range.
+
+// Builds every cluster's order from t and dt (one workgroup per cluster).
+__global__ void __launch_bounds__(kWG) cl_build_kernel(LevelArgs L)
+{
+    __shared__ int32_t h[64], base[64];
+    const int tid = threadIdx.x, c = blockIdx.x;
+    const int64_t o0 = L.offsets[c], o1 = L.offsets[c + 1];
+    if (tid < 64) h[tid] = 0;
+    __syncthreads();
+    for (int64_t i = o0 + tid; i < o1; i += kWG) atomicAdd(&h[log2_step(L.dt[i])], 1);
+    __syncthreads();
+    if (tid < 64) {
+        const int32_t k = h[tid];
+        const int32_t x = wave_inscan_i32(k);
+        base[tid] = x - k;
+        L.ccnt[c * 64 + tid] = k;
+        L.ccum[c * 64 + tid] = x;
+        const unsigned long long occ = __ballot(k > 0);
+        if (tid == 0) {
+            L.cmin[c] = occ ? __builtin_ctzll(occ) : 64;
+            L.cna[c] = 0;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = o0 + tid; i < o1; i += kWG) {
+        const int b = log2_step(L.dt[i]);
+        L.perm[o0 + atomicAdd(&base[b], 1)] = (int32_t)i;
+    }
+    if (c == 0 && tid == 0) {
+        L.misc[0] = L.misc[1];
+        *L.na = 0;
+        *L.na_prev = 0;
+    }
+}
+
+// Re-sorts every cluster's part of the last block by its new steps: one
+// workgroup per cluster, each on its own range.
+__global__ void __launch_bounds__(kWG) cl_resort_kernel(LevelArgs L)
+{
+    __shared__ LevelLds S;
+    const int tid = threadIdx.x, c = blockIdx.x;
+    if (*L.na_prev <= 0) return;
+    const int64_t T_prev = *L.T;
+    if (c == 0 && tid == 0) L.misc[0] = T_prev;
+    const int32_t m = L.cna[c];
+    if (m <= 0) return;
+    const int64_t o = L.offsets[c];
+    if ((int64_t)m > L.offsets[c + 1] - o) {
+        if (tid == 0)
+            __hip_atomic_store(&L.misc[4], (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    if (tid < 64) S.cnt[tid] = L.ccnt[c * 64 + tid];
+    level_resort(L, L.perm + o, L.tmp + o, m, __builtin_ctzll((unsigned long long)T_prev), S);
+    if (tid < 64) {
+        const int32_t k = S.cnt[tid];
+        L.ccnt[c * 64 + tid] = k;
+        L.ccum[c * 64 + tid] = wave_inscan_i32(k);
+        const unsigned long long occ = __ballot(k > 0);
+        if (tid == 0) L.cmin[c] = occ ? __builtin_ctzll(occ) : 64;
+    }
+}
+
+// Selects the next block of an ensemble and lists it grouped by cluster.
+// Every workgroup derives the block time and every cluster's count from
+// the same tables (nothing here writes them), lists the blocks of clusters
+// g, g + G, ... and records their sizes for the next re-sort; workgroup 0
+// publishes the block time, n_act, the clusters' first positions and the
+// sweep plan.
+__global__ void __launch_bounds__(kWG) cl_select_kernel(LevelArgs L, SweepArgs sa)
+{
+    __shared__ int32_t s_start[kLdsClusters + 1];
+    __shared__ int64_t s_min[kWG / 64];
+    __shared__ int32_t s_scan[kWG / 64];
+    const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
+    const int C = L.n_clusters;
+    const int64_t Tlast = L.misc[0];
+    int64_t bm = 64;
+    for (int c = tid; c < C; c += kWG) {
+        const int64_t v = L.cmin[c];
+        bm = v < bm ? v : bm;
+    }
+    bm = block_min_i64(bm, s_min);
+    int64_t Tn = INT64_MAX;
+    int zn = -1;
+    if (bm < 64) {
+        Tn = ((Tlast >> bm) + 1) << bm;
+        if (Tn <= L.T_end) zn = __builtin_ctzll((unsigned long long)Tn);
+    }
+    // thread t owns clusters [c0, c1): their counts, then their first positions
+    const int per = (C + kWG - 1) / kWG;
+    const int c0 = tid * per < C ? tid * per : C;
+    const int c1 = c0 + per < C ? c0 + per : C;
+    int32_t loc = 0;
+    for (int c = c0; c < c1; ++c) {
+        const int32_t k = zn >= 0 ? L.ccum[c * 64 + zn] : 0;
+        s_start[c] = k;
+        loc += k;
+    }
+    int32_t na;
+    int32_t run = block_exscan_i32(loc, s_scan, &na);
+    for (int c = c0; c < c1; ++c) {
+        const int32_t k = s_start[c];
+        s_start[c] = run;
+        run += k;
+    }
+    if (tid == 0) s_start[C] = na;
+    __syncthreads();
+    for (int c = g; c < C; c += G) {
+        const int32_t st = s_start[c], cnt = s_start[c + 1] - st;
+        const int32_t* src = L.perm + L.offsets[c];
+        for (int32_t k = tid; k < cnt; k += kWG) {
+            L.idx[st + k] = src[k];
+            sa.act_cluster[st + k] = c;
+        }
+        if (tid == 0) L.cna[c] = cnt;
+    }
+    if (g != 0) return;
+    for (int c = tid; c < C; c += kWG) sa.act_start[c] = s_start[c];
+    if (tid == 0) {
+        *L.T = Tn;
+        *L.na = na;
+        count_step(L.counters, Tn, na);
+    }
+    __syncthreads();   // act_start complete before the plan reads it
+    plan_body(sa, na);
 }
 
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
@@ -1201,17 +1140,22 @@ hipError_t launch_level_count(const LevelArgs& L, hipStream_t st)
 
 hipError_t launch_level_build(const LevelArgs& L, hipStream_t st)
 {
-    hipLaunchKernelGGL(level_build_kernel, dim3(level_grid(L.n)), dim3(kWG), 0, st, L);
+    if (L.n_clusters > 1)
+        hipLaunchKernelGGL(cl_build_kernel, dim3(L.n_clusters), dim3(kWG), 0, st, L);
+    else
+        hipLaunchKernelGGL(level_build_kernel, dim3(level_grid(L.n)), dim3(kWG), 0, st, L);
     return hipGetLastError();
 }
 
 hipError_t launch_level_select(const LevelArgs& L, const SweepArgs& sa, hipStream_t st)
 {
-    // one system: one workgroup (a grid over every XCD costs about 1.4 us
-    // per step even when the others leave at once, and the shared re-sort
-    // of large blocks did not pay for one system); clusters: kLevelGrid
-    const int grid = sa.n_clusters > 1 ? kLevelGrid : 1;
-    hipLaunchKernelGGL(level_select_kernel, dim3(grid), dim3(kWG), 0, st, L, sa);
+    if (L.n_clusters > 1) {
+        hipLaunchKernelGGL(cl_resort_kernel, dim3(L.n_clusters), dim3(kWG), 0, st, L);
+        const int grid = L.n_clusters < kSelectGrid ? L.n_clusters : kSelectGrid;
+        hipLaunchKernelGGL(cl_select_kernel, dim3(grid), dim3(kWG), 0, st, L, sa);
+    } else {
+        hipLaunchKernelGGL(level_select_kernel, dim3(1), dim3(kWG), 0, st, L, sa);
+    }
     return hipGetLastError();
 }
 

@@ -46,7 +46,10 @@
 namespace hm {
 namespace {
 
-constexpr int kMixedK = 16;   // FP32 run length before an FP64 flush
+// FP32 run lengths before an FP64 flush: kMixedK by default, kMixedKLong
+// (variant bit 2) halves the flushes' cost for more FP32 rounding per run
+constexpr int kMixedK = 16;
+constexpr int kMixedKLong = 32;
 
 #ifndef HM_MIXED_NR
 #define HM_MIXED_NR 0
@@ -233,23 +236,40 @@ __device__ __forceinline__ void add_near(Sum2F& S, const double o[7])
     S.pp.add_d(o[6]);
 }
 
-// The FP32 part of a mixed pair term, shared by every mixed form.
+// The FP32 part of a mixed pair term, shared by every mixed form.  first:
+// the run's first term starts the run sums (no zeroing between runs);
+// first_j: the same for the jerk (the paper-faithful mode never restarts
+// its jerk sum).
 __device__ __forceinline__ void far_terms(float dx, float dy, float dz, float dvx, float dvy,
-                                          float dvz, float r2, float ri, float mj, SumF& S)
+                                          float dvz, float ri, float mj, bool first,
+                                          bool first_j, SumF& S)
 {
-    (void)r2;
     const float mr = mj * ri;
     const float ri2 = ri * ri;
     const float mr3 = mr * ri2;
     const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
     const float b3 = (rv * ri2) * 3.0f;
-    S.pp += mr;
-    S.ax = fmaf(mr3, dx, S.ax);
-    S.ay = fmaf(mr3, dy, S.ay);
-    S.az = fmaf(mr3, dz, S.az);
-    S.jx = fmaf(mr3, fmaf(-b3, dx, dvx), S.jx);
-    S.jy = fmaf(mr3, fmaf(-b3, dy, dvy), S.jy);
-    S.jz = fmaf(mr3, fmaf(-b3, dz, dvz), S.jz);
+    const float jx = fmaf(-b3, dx, dvx), jy = fmaf(-b3, dy, dvy), jz = fmaf(-b3, dz, dvz);
+    if (first) {
+        S.pp = mr;
+        S.ax = mr3 * dx;
+        S.ay = mr3 * dy;
+        S.az = mr3 * dz;
+    } else {
+        S.pp += mr;
+        S.ax = fmaf(mr3, dx, S.ax);
+        S.ay = fmaf(mr3, dy, S.ay);
+        S.az = fmaf(mr3, dz, S.az);
+    }
+    if (first_j) {
+        S.jx = mr3 * jx;
+        S.jy = mr3 * jy;
+        S.jz = mr3 * jz;
+    } else {
+        S.jx = fmaf(mr3, jx, S.jx);
+        S.jy = fmaf(mr3, jy, S.jy);
+        S.jz = fmaf(mr3, jz, S.jz);
+    }
 }
 
 // Near-field test and parameters of one work item.
@@ -264,12 +284,12 @@ struct NearF {
 // caller evaluates the (rare) near pairs in FP64 later.
 __device__ __forceinline__ bool far_pair(float dx, float dy, float dz, float dvx, float dvy,
                                          float dvz, float eps2f, float near2f, float mj,
-                                         SumF& S)
+                                         bool first, bool first_j, SumF& S)
 {
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
     const bool far = !(r2 <= near2f);
     const float ri = far ? rsq_f32(r2) : 0.0f;
-    far_terms(dx, dy, dz, dvx, dvy, dvz, r2, ri, mj, S);
+    far_terms(dx, dy, dz, dvx, dvy, dvz, ri, mj, first, first_j, S);
     return far;
 }
 
@@ -283,11 +303,11 @@ __device__ __forceinline__ bool near_test(float dx, float dy, float dz, float ep
 // Cast form: FP64 differences rounded to FP32.
 __device__ __forceinline__ bool pair_mixed(const I64& I, float eps2f, float near2f, double xj,
                                            double yj, double zj, double vxj, double vyj,
-                                           double vzj, float mj, SumF& S)
+                                           double vzj, float mj, bool first, SumF& S)
 {
     return far_pair((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z),
                     (float)(vxj - I.vx), (float)(vyj - I.vy), (float)(vzj - I.vz), eps2f,
-                    near2f, mj, S);
+                    near2f, mj, first, first, S);
 }
 
 __device__ __forceinline__ bool near_mixed_test(const I64& I, float eps2f, float near2f,
@@ -330,12 +350,12 @@ __device__ __forceinline__ double join_diff(float jh, float jl, float ih, float 
 }
 
 __device__ __forceinline__ bool pair_split(const I32S& I, float eps2f, float near2f,
-                                           const float* J, float mj, SumF& S)
+                                           const float* J, float mj, bool first, SumF& S)
 {
     return far_pair((J[0] - I.xh) + (J[1] - I.xl), (J[2] - I.yh) + (J[3] - I.yl),
                     (J[4] - I.zh) + (J[5] - I.zl), (J[6] - I.vxh) + (J[7] - I.vxl),
                     (J[8] - I.vyh) + (J[9] - I.vyl), (J[10] - I.vzh) + (J[11] - I.vzl), eps2f,
-                    near2f, mj, S);
+                    near2f, mj, first, first, S);
 }
 
 __device__ __forceinline__ bool near_split_test(const I32S& I, float eps2f, float near2f,
@@ -368,10 +388,10 @@ struct I64SP {  // i-particle: FP64 position, FP32 velocity
 
 __device__ __forceinline__ bool pair_sp(const I64SP& I, float eps2f, float near2f, double xj,
                                         double yj, double zj, float vxj, float vyj, float vzj,
-                                        float mj, SumF& S)
+                                        float mj, bool first, SumF& S)
 {
     return far_pair((float)(xj - I.x), (float)(yj - I.y), (float)(zj - I.z), vxj - I.vx,
-                    vyj - I.vy, vzj - I.vz, eps2f, near2f, mj, S);
+                    vyj - I.vy, vzj - I.vz, eps2f, near2f, mj, first, false, S);
 }
 
 __device__ __forceinline__ bool near_sp_test(const I64SP& I, float eps2f, float near2f,
@@ -392,11 +412,11 @@ __device__ __forceinline__ void near_sp(const I64SP& I, const NearF& nf, double 
 
 // Flush of the paper-faithful mode: acceleration and potential runs go to
 // the FP64 sums, the jerk stays in its FP32 accumulator (never flushed).
-__device__ __forceinline__ void flush_keep_jerk(SumF& f, SumD& d)
+// (No flush clears the run sums: the next run's first term restarts them.)
+__device__ __forceinline__ void flush_keep_jerk(const SumF& f, SumD& d)
 {
     d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
     d.pp += (double)f.pp;
-    f.ax = f.ay = f.az = f.pp = 0.0f;
 }
 
 // Error estimate of the mixed paths: the squares of each FP32 run sum.
@@ -407,22 +427,20 @@ __device__ __forceinline__ void add_estimate(const SumF& f, RUN& d)
     d.ej = fmaf(f.jx, f.jx, fmaf(f.jy, f.jy, fmaf(f.jz, f.jz, d.ej)));
 }
 
-__device__ __forceinline__ void flush(SumF& f, SumD& d)
+__device__ __forceinline__ void flush(const SumF& f, SumD& d)
 {
     add_estimate(f, d);
     d.ax += (double)f.ax; d.ay += (double)f.ay; d.az += (double)f.az;
     d.jx += (double)f.jx; d.jy += (double)f.jy; d.jz += (double)f.jz;
     d.pp += (double)f.pp;
-    f.zero();
 }
 
-__device__ __forceinline__ void flush(SumF& f, Sum2F& d)
+__device__ __forceinline__ void flush(const SumF& f, Sum2F& d)
 {
     add_estimate(f, d);
     d.ax.add(f.ax); d.ay.add(f.ay); d.az.add(f.az);
     d.jx.add(f.jx); d.jy.add(f.jy); d.jz.add(f.jz);
     d.pp.add(f.pp);
-    f.zero();
 }
 
 // LDS tile of j-particles (SoA), FP64 path.
@@ -439,16 +457,22 @@ struct Tile {
 constexpr int kTJPad = kTJ + 64;
 constexpr double kFarAway = 1e30;
 
-// Mixed (cast form): FP64 coordinates; the mass as FP32 hi and lo words
-// (hi for the FP32 terms, hi + lo for the FP64 near terms).
+// FP32 hi and lo words of a mass (hi for the FP32 terms, hi + lo for the
+// FP64 near terms), side by side: a tile's per-j records all have an
+// 8-byte stride and are addressed from one register.
+struct MassHL {
+    float hi, lo;
+};
+
+// Mixed (cast form): FP64 coordinates and the mass words.
 struct TileM {
     double x[kTJPad], y[kTJPad], z[kTJPad], vx[kTJPad], vy[kTJPad], vz[kTJPad];
-    float m[kTJPad], mlo[kTJPad];
+    MassHL m[kTJPad];
     __device__ void pad(int k)
     {
         x[k] = y[k] = z[k] = kFarAway;
         vx[k] = vy[k] = vz[k] = 0.0;
-        m[k] = mlo[k] = 0.0f;
+        m[k] = MassHL{0.0f, 0.0f};
     }
 };
 
@@ -520,7 +544,7 @@ __device__ __forceinline__ void tile_pot(const Tile<double>& T, int cnt, int sub
 }
 
 
-// Mixed tile loops.  Each lane takes runs of kMixedK of its j (every L-th
+// Mixed tile loops.  Each lane takes runs of KR of its j (every L-th
 // j of the tile).  A run's pair terms are summed in FP32 with no branch and
 // no per-lane guard: slots past the tile's end hold zero-mass particles far
 // away (see pad_tile), so every lane runs the same trip count, and near
@@ -543,26 +567,29 @@ __device__ __forceinline__ uint32_t run_hit_bit(uint64_t far_ballot, uint32_t bi
     return t;
 }
 
-template <typename FAR, typename NEARFN, typename FLUSH>
+template <int KR, typename FAR, typename NEARFN, typename FLUSH, typename ZERO>
 __device__ __forceinline__ void mixed_runs(int cnt, int sub, int L, FAR far, NEARFN near_fn,
-                                           FLUSH flush_fn)
+                                           FLUSH flush_fn, ZERO zero_fn)
 {
-    const int step = kMixedK * L;
+    static_assert(KR >= 1 && KR <= 32, "a run's near hits are one 32-bit word");
+    const int step = KR * L;
     for (int jb = 0; jb < cnt; jb += step) {
         const int je = (jb + step < cnt) ? jb + step : cnt;
         const int nk = (je - jb + L - 1) / L;   // j per lane in this run (uniform)
         uint32_t hit = 0;
-        // every lane of the wave is active here: a lane that met a near pair
-        // at its k-th j clears its bit of that j's ballot.  (The ballot is a
-        // convergent operation, which rules out unrolling a loop of unknown
-        // trip count: full runs take the constant-trip form.)
-        if (nk == kMixedK) {
+        // every lane of the wave is active here: far() returns the AND of
+        // its particles' ballots of "far", so a lane that met a near pair at
+        // its k-th j clears its bit.  (A ballot is a convergent operation,
+        // which rules out unrolling a loop of unknown trip count: full runs
+        // take the constant-trip form, whose first term starts the run sums.)
+        if (nk == KR) {
 #pragma unroll
-            for (int k = 0; k < kMixedK; ++k)
-                hit |= run_hit_bit(__builtin_amdgcn_ballot_w64(far(jb + sub + k * L)), 1u << k);
+            for (int k = 0; k < KR; ++k)
+                hit |= run_hit_bit(far(jb + sub + k * L, k == 0), 1u << k);
         } else {
+            zero_fn();
             for (int k = 0; k < nk; ++k)
-                hit |= run_hit_bit(__builtin_amdgcn_ballot_w64(far(jb + sub + k * L)), 1u << k);
+                hit |= run_hit_bit(far(jb + sub + k * L, false), 1u << k);
         }
         flush_fn();
         while (__builtin_expect(hit != 0, 0)) {
@@ -573,28 +600,30 @@ __device__ __forceinline__ void mixed_runs(int cnt, int sub, int L, FAR far, NEA
     }
 }
 
-template <int IPL, typename RUN>
+template <int IPL, int KR, typename RUN>
 __device__ __forceinline__ void tile_mixed(const TileM& T, int cnt, int sub, int L, int tb,
                                            const int (&ii)[IPL], const I64 (&I)[IPL],
                                            float eps2f, const NearF& nf, SumF (&f)[IPL],
                                            RUN (&S)[IPL])
 {
-    mixed_runs(
+    mixed_runs<KR>(
         cnt, sub, L,
-        [&](int jj) {
+        [&](int jj, bool first) {
             const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
             const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
-            const float mj = T.m[jj];
-            bool fr = true;
+            const float mj = T.m[jj].hi;
+            uint64_t fr = ~0ull;
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
-                fr &= pair_mixed(I[q], eps2f, nf.near2f, xj, yj, zj, vxj, vyj, vzj, mj, f[q]);
+                fr &= __builtin_amdgcn_ballot_w64(pair_mixed(I[q], eps2f, nf.near2f, xj, yj, zj,
+                                                             vxj, vyj, vzj, mj, first, f[q]));
             return fr;
         },
         [&](int jj) {
             const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
             const double vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj];
-            const double mj = (double)T.m[jj] + (double)T.mlo[jj];
+            const MassHL mw = T.m[jj];
+            const double mj = (double)mw.hi + (double)mw.lo;
 #pragma unroll
             for (int q = 0; q < IPL; ++q) {
                 if (near_mixed_test(I[q], eps2f, nf.near2f, xj, yj, zj))
@@ -605,25 +634,31 @@ __device__ __forceinline__ void tile_mixed(const TileM& T, int cnt, int sub, int
         [&]() {
 #pragma unroll
             for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+        },
+        [&]() {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) f[q].zero();
         });
 }
 
-template <int IPL, typename RUN>
+template <int IPL, int KR, typename RUN>
 __device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int L, int tb,
                                            const int (&ii)[IPL], const I32S (&I)[IPL],
                                            float eps2f, const NearF& nf, SumF (&f)[IPL],
                                            RUN (&S)[IPL])
 {
-    mixed_runs(
+    mixed_runs<KR>(
         cnt, sub, L,
-        [&](int jj) {
+        [&](int jj, bool first) {
             float J[12];
 #pragma unroll
             for (int w = 0; w < 12; ++w) J[w] = T.c[w][jj];
             const float mj = T.m[jj];
-            bool fr = true;
+            uint64_t fr = ~0ull;
 #pragma unroll
-            for (int q = 0; q < IPL; ++q) fr &= pair_split(I[q], eps2f, nf.near2f, J, mj, f[q]);
+            for (int q = 0; q < IPL; ++q)
+                fr &= __builtin_amdgcn_ballot_w64(
+                    pair_split(I[q], eps2f, nf.near2f, J, mj, first, f[q]));
             return fr;
         },
         [&](int jj) {
@@ -641,24 +676,29 @@ __device__ __forceinline__ void tile_split(const TileS& T, int cnt, int sub, int
         [&]() {
 #pragma unroll
             for (int q = 0; q < IPL; ++q) flush(f[q], S[q]);
+        },
+        [&]() {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) f[q].zero();
         });
 }
 
-template <int IPL>
+template <int IPL, int KR>
 __device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L, int tb,
                                         const int (&ii)[IPL], const I64SP (&I)[IPL],
                                         float eps2f, const NearF& nf, SumF (&f)[IPL],
                                         SumD (&S)[IPL])
 {
-    mixed_runs(
+    mixed_runs<KR>(
         cnt, sub, L,
-        [&](int jj) {
+        [&](int jj, bool first) {
             const double xj = T.x[jj], yj = T.y[jj], zj = T.z[jj];
             const float vxj = T.vx[jj], vyj = T.vy[jj], vzj = T.vz[jj], mj = T.m[jj];
-            bool fr = true;
+            uint64_t fr = ~0ull;
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
-                fr &= pair_sp(I[q], eps2f, nf.near2f, xj, yj, zj, vxj, vyj, vzj, mj, f[q]);
+                fr &= __builtin_amdgcn_ballot_w64(pair_sp(I[q], eps2f, nf.near2f, xj, yj, zj,
+                                                          vxj, vyj, vzj, mj, first, f[q]));
             return fr;
         },
         [&](int jj) {
@@ -675,6 +715,12 @@ __device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L
         [&]() {
 #pragma unroll
             for (int q = 0; q < IPL; ++q) flush_keep_jerk(f[q], S[q]);
+        },
+        [&]() {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                f[q].ax = f[q].ay = f[q].az = f[q].pp = 0.0f;
+            }
         });
 }
 
@@ -717,8 +763,11 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[kRows])
 // SEL: the workgroup first selects the block itself (one system of
 // n <= kFusedSelMax; the active list stays in LDS) and computes the plan;
 // workgroup 0 publishes list, n_act, T, plan and counters for the corrector.
-template <int PREC, bool POT_ONLY, int IPL, bool SPLIT, bool SEL = false>
-__global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2) ? 3 : 1) sweep_kernel(SweepArgs a)
+template <int PREC, bool POT_ONLY, int IPL, bool SPLIT, bool SEL = false, int KR = kMixedK>
+// (The split two-per-lane form with FP64 running sums fits three waves per
+// SIMD without spilling; the two-float and fused-selection forms do not.)
+__global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2 && PREC == 1 && !SEL) ? 3 : 1)
+sweep_kernel(SweepArgs a)
 {
     static_assert(!SEL || !POT_ONLY, "the fused selection is for block steps");
     static_assert(!SPLIT || (PREC == 1 || PREC == 2), "split form is for the mixed modes");
@@ -908,8 +957,15 @@ __global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2) ? 3 : 1) sweep_kernel
                         T.vy[tid] = w[1];
                         T.vz[tid] = w[2];
                         const double mj = a.m[jg];
-                        T.m[tid] = (MT)mj;
-                        if constexpr (PREC != 0) T.mlo[tid] = (float)(mj - (double)(MT)mj);
+                        if constexpr (PREC == 0) {
+                            T.m[tid] = mj;
+                        } else if constexpr (PREC == 3) {
+                            T.m[tid] = (float)mj;
+                            T.mlo[tid] = (float)(mj - (double)(float)mj);
+                        } else {
+                            const float h = (float)mj;
+                            T.m[tid] = MassHL{h, (float)(mj - (double)h)};
+                        }
                     }
                 }
             } else if constexpr (kMixed) {
@@ -933,11 +989,11 @@ __global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2) ? 3 : 1) sweep_kernel
                     else           tile_f64<false, IPL>(T, cnt, sub, L, tb, ii, I, eps2, S);
                 }
             } else if constexpr (SPLIT) {
-                tile_split<IPL>(T, cnt, sub, L, (int)tb, ii, IS, eps2f, nf, F, S);
+                tile_split<IPL, KR>(T, cnt, sub, L, (int)tb, ii, IS, eps2f, nf, F, S);
             } else if constexpr (PREC == 3) {
-                tile_sp<IPL>(T, cnt, sub, L, (int)tb, ii, ISP, eps2f, nf, F, S);
+                tile_sp<IPL, KR>(T, cnt, sub, L, (int)tb, ii, ISP, eps2f, nf, F, S);
             } else {
-                tile_mixed<IPL>(T, cnt, sub, L, (int)tb, ii, I, eps2f, nf, F, S);
+                tile_mixed<IPL, KR>(T, cnt, sub, L, (int)tb, ii, I, eps2f, nf, F, S);
             }
         }
 
@@ -1108,22 +1164,30 @@ SweepFn sweep_sel_fn(int precision, int variant)
 }
 
 // variant: bit 0 -> two active particles per lane; bit 1 -> split
-// differences (MIXED and MIXED_2F only; FP64 and MIXED_SP ignore it).
+// differences (MIXED and MIXED_2F only; FP64 and MIXED_SP ignore it); bit 2
+// -> FP32 runs of kMixedKLong (the mixed precisions; FP64 ignores it).
+template <int PREC, int IPL, bool SPLIT>
+SweepFn mixed_fn(bool long_runs)
+{
+    return long_runs ? sweep_kernel<PREC, false, IPL, SPLIT, false, kMixedKLong>
+                     : sweep_kernel<PREC, false, IPL, SPLIT, false, kMixedK>;
+}
+
 SweepFn sweep_fn(int precision, int variant, bool pot_only)
 {
     if (pot_only) return sweep_kernel<0, true, 1, false>;
     const bool two = (variant & 1) != 0;
     const bool spl = (variant & 2) != 0;
+    const bool lng = (variant & 4) != 0;
     if (precision == 0)
         return two ? sweep_kernel<0, false, 2, false> : sweep_kernel<0, false, 1, false>;
     if (precision == 1) {
-        if (spl) return two ? sweep_kernel<1, false, 2, true> : sweep_kernel<1, false, 1, true>;
-        return two ? sweep_kernel<1, false, 2, false> : sweep_kernel<1, false, 1, false>;
+        if (spl) return two ? mixed_fn<1, 2, true>(lng) : mixed_fn<1, 1, true>(lng);
+        return two ? mixed_fn<1, 2, false>(lng) : mixed_fn<1, 1, false>(lng);
     }
-    if (precision == 3)
-        return two ? sweep_kernel<3, false, 2, false> : sweep_kernel<3, false, 1, false>;
-    if (spl) return two ? sweep_kernel<2, false, 2, true> : sweep_kernel<2, false, 1, true>;
-    return two ? sweep_kernel<2, false, 2, false> : sweep_kernel<2, false, 1, false>;
+    if (precision == 3) return two ? mixed_fn<3, 2, false>(lng) : mixed_fn<3, 1, false>(lng);
+    if (spl) return two ? mixed_fn<2, 2, true>(lng) : mixed_fn<2, 1, true>(lng);
+    return two ? mixed_fn<2, 2, false>(lng) : mixed_fn<2, 1, false>(lng);
 }
 
 }  // namespace
@@ -1201,17 +1265,26 @@ hipError_t launch_reduce_refine(const SweepArgs& a_in, const SweepArgs& ra_in, i
 }
 
 hipError_t launch_force(const SweepArgs& a_in, const SweepArgs* ra, int precision, int variant,
-                        int grid, bool pot_only, hipStream_t st)
+                        int grid, bool pot_only, hipStream_t st, const hipEvent_t* marks)
 {
     SweepArgs a = a_in;
     a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
+    if (marks) {
+        const hipError_t e = hipEventRecord(marks[0], st);
+        if (e != hipSuccess) return e;
+    }
     launch_sweep_kernels(a, precision, variant, grid, pot_only, false, st);
+    if (marks) {
+        const hipError_t e = hipEventRecord(marks[1], st);
+        if (e != hipSuccess) return e;
+    }
     const int rgrid = reduce_grid(a.n_act_max);
     if (pot_only) {
         hipLaunchKernelGGL(reduce_kernel<true>, dim3(rgrid), dim3(kWG), 0, st, a);
     } else if (ra && a.refine) {
-        launch_reduce_refine(a, *ra, variant, grid, st);
+        const hipError_t e = launch_reduce_refine(a, *ra, variant, grid, st);
+        if (e != hipSuccess) return e;
         SweepArgs r = *ra;
         r.ipl = a.ipl;
         hipLaunchKernelGGL(refine_scatter_kernel, dim3(rgrid), dim3(kWG), 0, st, a, r);

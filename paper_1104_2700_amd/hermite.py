@@ -73,6 +73,8 @@ _SIGS = {
     "hermite_select_block": ([_P, _PS, _P, _P, _P, _i64, _P]),
     "hermite_predict": ([_P, _PS, _P, _i64, _P, _P]),
     "hermite_force_jerk": ([_P, _PS, _PC, _P, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _P]),
+    "hermite_force_jerk_timed": ([_P, _PS, _PC, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _i32,
+                                  ctypes.POINTER(_d), _P]),
     "hermite_force_jerk_noalloc": ([_PS, _PC, _P, _P, _i32, _d, ctypes.c_int, _P, _P, _P, _P]),
     "hermite_correct": ([_P, _PS, _P, _P, _i32, _P, _i64, _P, _P, _P, _PD, _P, _P]),
     "hermite_init_dt": ([_P, _PS, _PD, _P]),
@@ -267,6 +269,26 @@ class Context:
                                       int(precision), _ptr(acc), _ptr(jerk), _ptr(pot),
                                       _stream(stream)), "hermite_force_jerk")
         return acc, jerk, pot
+
+    def force_jerk_timed(self, s: State, idx, eps2, precision=FP64, reps=10, acc=None,
+                         jerk=None, pot=None, clusters=None, stream=None):
+        """Runs the sweep ``reps`` times with HIP events around its phases on
+        the launch stream; returns (acc, jerk, pot, ms) where ms holds the
+        average milliseconds of the plan kernel, the sweep kernel(s), the
+        finishing kernels and the whole call."""
+        n_act = s.n if idx is None else int(idx.shape[0])
+        f64 = dict(dtype=torch.float64, device=s.x.device)
+        acc = torch.empty(3, n_act, **f64) if acc is None else acc
+        jerk = torch.empty(3, n_act, **f64) if jerk is None else jerk
+        pot = torch.empty(n_act, **f64) if pot is None else pot
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        ms = (ctypes.c_double * 4)()
+        _check(lib.hermite_force_jerk_timed(self.h, ctypes.byref(s.c()), _cl(clusters), _ptr(idx),
+                                            n_act, float(eps2), int(precision), _ptr(acc),
+                                            _ptr(jerk), _ptr(pot), int(reps), ms,
+                                            _stream(stream)), "hermite_force_jerk_timed")
+        return acc, jerk, pot, {"plan": ms[0], "sweep": ms[1], "finish": ms[2], "total": ms[3]}
 
     def correct(self, s: State, idx, acc, jerk, pot, params, T_dev=None, T_host=0,
                 n_act_dev=None, n_act_max=None, crit_out=None, stream=None):

@@ -101,7 +101,9 @@ def block_run(ctx, s, eps2, params, t_end, precision, clusters=None,
     c1 = ctx.counters()
     hist = (np.array(ctx.block_histogram()) - h0).tolist()
     rel = np.abs((e1 - e0) / e0)
+    lv = TB - np.log2(s.dt.cpu().numpy()).astype(np.int64)
     return {
+        "dt_levels_final": {int(k): int(c) for k, c in enumerate(np.bincount(lv)) if c},
         "t_end": t_end, "wall_s": wall, "block_steps": steps, "interactions": inter,
         "interactions_per_s": inter / wall, "gflops_60": 60.0 * inter / wall / 1e9,
         "clamped_steps": c1["clamped"] - c0["clamped"],
@@ -447,10 +449,18 @@ def main(argv=None):
                     help="timestep criterion form (e4 only)")
     ap.add_argument("--start-div", type=float, default=0.0,
                     help="start-up factor = steady factor / this (0: the steady factor)")
+    ap.add_argument("--tick-bits", type=int, default=None,
+                    help="time tick 2^-tick_bits (default 20)")
+    ap.add_argument("--k-max", type=int, default=None,
+                    help="finest step 2^-k_max (default 20; at most tick_bits)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    global START_DIV
+    global START_DIV, TB, K_MAX
     START_DIV = a.start_div
+    if a.tick_bits is not None:
+        TB = a.tick_bits
+    if a.k_max is not None:
+        K_MAX = a.k_max
     ctx = H.Context(0)
     kw = {}
     if a.t_end is not None:
@@ -465,6 +475,8 @@ def main(argv=None):
     res = RUNNERS[a.name](ctx, **kw)
     res["device"] = torch.cuda.get_device_name(0)
     res["start_div"] = START_DIV
+    res["tick_bits"] = TB
+    res["k_min_max"] = [K_MIN, K_MAX]
     txt = json.dumps(res)
     if a.out:
         with open(a.out, "w") as f:

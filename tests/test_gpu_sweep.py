@@ -68,7 +68,8 @@ def test_fp64_sweep_parity(H, ctx, n, n_act):
 @pytest.fixture
 def variant(H, ctx, request):
     """Installs launch-shape variant `request.param` for every precision
-    (bit 0: two particles per lane, bit 1: split FP32 differences)."""
+    (bit 0: two particles per lane, bit 1: split FP32 differences, bit 2:
+    FP32 runs of 32 terms)."""
     saved = [ctx.get_tuning(p) for p in range(4)]
     for p in range(4):
         t = ctx.get_tuning(p)
@@ -103,7 +104,7 @@ def fp32(H, ctx):
     restore_policy(ctx, saved)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3], indirect=True)
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7], indirect=True)
 @pytest.mark.parametrize("prec", ["mixed", "mixed2f"])
 @pytest.mark.parametrize("n,n_act", [(1, 1), (64, 7), (257, 257), (1024, 1024),
                                      (4097, 65), (5000, 1), (6000, 6000)])
@@ -200,7 +201,7 @@ def test_mixed_ensemble_straddling_threshold(H, ctx):
         check_mixed("pot%d" % c, P.cpu().numpy()[sample][None], rp[None], cond[2])
 
 
-@pytest.mark.parametrize("variant", [0, 1], indirect=True)
+@pytest.mark.parametrize("variant", [0, 1, 4, 5], indirect=True)
 @pytest.mark.parametrize("n,n_act", [(1, 1), (64, 7), (257, 257), (1024, 1024),
                                      (4097, 65), (5000, 1)])
 def test_mixed_sp_sweep_parity(H, ctx, variant, n, n_act):
@@ -281,11 +282,12 @@ def test_zero_softening_two_body(H, ctx):
         assert np.allclose(pot.cpu().numpy(), rp, rtol=tol, atol=0)
 
 
-@pytest.mark.parametrize("variant", [1, 3], indirect=True)
+@pytest.mark.parametrize("variant", [1, 3, 5, 7], indirect=True)
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_full_sweep_65536_sampled(H, ctx, variant, prec):
     """The full N = 65536 Plummer sweep (both forms of the FP32 differences:
-    FP64 subtraction then cast, variant 1, and FP32 hi/lo words, variant 3),
+    FP64 subtraction then cast, variants 1 and 5, and FP32 hi/lo words,
+    variants 3 and 7; FP32 runs of 16 or 32 terms),
     checked on the 1024 sampled particles against the oracle and, for the
     mixed precisions, on all 65536 particles against the FP64 sweep (itself
     checked on the sample); plus the momentum invariants over all
