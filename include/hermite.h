@@ -356,7 +356,7 @@ int hermite_get_tuning(hermite_ctx* ctx, int precision, hermite_tuning* out);
  *
  * Refinement.  HERMITE_MIXED and HERMITE_MIXED_2F also estimate each
  * particle's remaining FP32 error from its sums (the squares of the FP32
- * partial sums over runs of 16 j) and sum a particle again in FP64 when
+ * partial sums over runs of 16 or 32 j) and sum a particle again in FP64 when
  * the estimate exceeds 4e-8 of its acceleration or jerk: particles whose
  * sums almost cancel.  The count is reported by hermite_counters.
  *
@@ -369,6 +369,21 @@ int hermite_set_mixed_policy(hermite_ctx* ctx, int precision, double near_factor
                              int64_t fp64_below);
 int hermite_get_mixed_policy(hermite_ctx* ctx, int precision, double* near_factor,
                              int64_t* fp64_below);
+
+/* Small blocks of HERMITE_MIXED and HERMITE_MIXED_2F.  A force sweep (or a
+ * block step's sweep) of fewer than fp64_inter_below interactions
+ * (sum over systems of active particles x system size) is done in FP64:
+ * such a sweep is bound by launch and memory latency, where the FP32
+ * arithmetic saves less than the refinement's kernels cost.  Decided on
+ * the device from the block's active count, so a captured step adapts to
+ * every block.  Default 5e7 (about 760 active particles of a 65536-particle
+ * system); 0 sweeps every block with FP32 pair arithmetic.  EINVAL for
+ * another precision or a negative value.  Setting it drops captured step
+ * graphs. */
+int hermite_set_mixed_small_blocks(hermite_ctx* ctx, int precision,
+                                   int64_t fp64_inter_below);
+int hermite_get_mixed_small_blocks(hermite_ctx* ctx, int precision,
+                                   int64_t* fp64_inter_below);
 int hermite_set_tuning(hermite_ctx* ctx, int precision,
                        const hermite_tuning* in);
 

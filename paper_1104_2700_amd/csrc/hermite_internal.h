@@ -31,6 +31,8 @@ struct SweepPlan {
     int32_t s_max;        // largest number of j-chunks of any cluster
     int64_t jc;           // j-chunk length (multiple of kTJ)
     int32_t total_items;  // work items (cluster, i-tile, j-chunk)
+    int32_t fp64_all;     // mixed precisions: this block is swept in FP64 (its
+                          // interactions are below SweepArgs::fp64_inter_below)
 };
 
 // Everything the plan, sweep and reduce kernels read.  Passed by value.
@@ -71,6 +73,10 @@ struct SweepArgs {
     // N_c < fp64_below are swept in FP64 altogether
     double near_factor;
     int64_t fp64_below;
+    // mixed precisions: blocks of fewer interactions than this are swept in
+    // FP64 (latency-bound there, where the refinement's launches would cost
+    // more than FP32 arithmetic saves); 0: never
+    int64_t fp64_inter_below;
     // nonzero: the reduce stage flags particles whose estimated mixed
     // error is too large (ref_pos[p] = 1) and plans their FP64 refinement
     int32_t refine;
@@ -80,9 +86,9 @@ struct SweepArgs {
     int32_t* ref_tmp;          // [n_act_max] flagged positions, compacted per reduce unit
     int32_t* ref_ucnt;         // [n_act_max / 4 + 1] flagged per reduce unit, then its first slot
     int32_t* ref_ccnt;         // [C] flagged per cluster, then placement cursors
-    // items a sweep launch takes: 0 all; 1 those of systems with
-    // N_c >= fp64_below (the mixed kernel of a mixed ensemble sweep); 2 those
-    // with N_c < fp64_below (its FP64 kernel)
+    // items a sweep launch takes: 0 all; 1 the mixed kernel's: systems with
+    // N_c >= fp64_below in a block the plan has not put in FP64 (fp64_all);
+    // 2 the FP64 kernel's: the others
     int32_t kind;
     // counters (may be null): [0] steps, [1] interactions, [4] last n_act
     int64_t* counters;

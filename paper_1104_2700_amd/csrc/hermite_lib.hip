@@ -73,6 +73,7 @@ struct hermite_ctx {
     hermite_tuning tuning[4];
     double near_factor[4];     // near-field radius factor per precision
     int64_t fp64_below[4];     // systems smaller than this are swept in FP64
+    int64_t fp64_inter_below[4];   // blocks of fewer interactions are swept in FP64
     // scratch
     Buf plan, act_start, act_cnt, chunks, item_off, partial;
     // refinement of mixed sweeps: flags and lists, the refine sweep's plan,
@@ -225,6 +226,16 @@ int64_t default_fp64_below(int precision)
     return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 8192 : 0;
 }
 
+// Blocks of fewer interactions than this are swept in FP64 by the mixed
+// precisions: a small block's sweep is bound by launch and load latency,
+// and the refinement's extra launches cost more than FP32 arithmetic saves
+// (MI355X, N = 65536, autotuned shapes: FP64 / mixed 57 / 71 us at 512
+// active particles, 100 / 103 at 1024, 183 / 176 at 2048).
+int64_t default_fp64_inter_below(int precision)
+{
+    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 50000000 : 0;
+}
+
 // Device scratch of one force sweep and of its refinement, as pointers
 // (context buffers, or the static scratch of hermite_force_jerk_noalloc).
 struct SweepScratch {
@@ -265,7 +276,8 @@ void fill_sweep(const SweepScratch& sc, const hermite_state* s, const hermite_cl
                 const double* xp, const double* vp, const int32_t* idx,
                 const int32_t* n_act_dev, int32_t n_act_max, double eps2, int precision,
                 const hermite_tuning& tu, double near_factor, int64_t fp64_below,
-                int64_t* counters, double* acc, double* jerk, double* pot, SweepArgs* a)
+                int64_t fp64_inter_below, int64_t* counters, double* acc, double* jerk,
+                double* pot, SweepArgs* a)
 {
     std::memset(a, 0, sizeof *a);
     a->xp = xp;
@@ -291,6 +303,8 @@ void fill_sweep(const SweepScratch& sc, const hermite_state* s, const hermite_cl
     a->min_j_per_lane = tu.min_j_per_lane;
     a->near_factor = precision == HERMITE_FP64 ? 0.0 : near_factor;
     a->fp64_below = precision == HERMITE_FP64 ? 0 : fp64_below;
+    a->fp64_inter_below =
+        (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? fp64_inter_below : 0;
     a->refine = uses_refine(precision, a->n_cmax, a->fp64_below) ? 1 : 0;
     if (a->refine) {
         a->ref_pos = sc.ref_pos;
@@ -329,6 +343,7 @@ void fill_refine(const SweepScratch& sc, const SweepArgs& a, SweepArgs* ra)
     ra->refine = 0;
     ra->near_factor = 0.0;
     ra->fp64_below = 0;
+    ra->fp64_inter_below = 0;
     ra->kind = 0;
     ra->counters = nullptr;
     ra->sel_dt = nullptr;
@@ -403,7 +418,7 @@ int prepare_sweep(hermite_ctx* c, const hermite_state* s, const hermite_clusters
     CHECK(ctx_scratch(c, C, n_act_max, refine, &sc));
     CHECK(ensure(c, c->counters, sizeof(int64_t) * kCounters));
     fill_sweep(sc, s, cl, xp, vp, idx, n_act_dev, n_act_max, eps2, precision, tu, nfac, f64b,
-               (int64_t*)c->counters.p, acc, jerk, pot, a);
+               c->fp64_inter_below[precision], (int64_t*)c->counters.p, acc, jerk, pot, a);
     return HERMITE_OK;
 }
 
@@ -781,6 +796,7 @@ int hermite_create(int device, hermite_ctx** out)
         c->tuning[p] = default_tuning(c, p);
         c->near_factor[p] = default_near_factor(p);
         c->fp64_below[p] = default_fp64_below(p);
+        c->fp64_inter_below[p] = default_fp64_inter_below(p);
     }
     int rc = ensure(c, c->counters, sizeof(int64_t) * kCounters);
     if (rc == HERMITE_OK && hipMemset(c->counters.p, 0, sizeof(int64_t) * kCounters) != hipSuccess)
@@ -956,8 +972,8 @@ int hermite_force_jerk_noalloc(const hermite_state* s, const hermite_clusters* c
     const hermite_tuning tu = default_tuning_for(nd->n_cu);
     SweepArgs a, ra;
     fill_sweep(sc, s, cl, s->xp, s->vp, idx, n_act_dev, n_act_max, eps2, precision, tu,
-               default_near_factor(precision), default_fp64_below(precision), nullptr, acc,
-               jerk, pot, &a);
+               default_near_factor(precision), default_fp64_below(precision),
+               default_fp64_inter_below(precision), nullptr, acc, jerk, pot, &a);
     if (a.refine) fill_refine(sc, a, &ra);
     const int grid = std::max(1, nd->n_cu * tu.wg_per_cu);
     HIP_OK(launch_force(a, a.refine ? &ra : nullptr, precision, tu.variant, grid, false,
@@ -1282,6 +1298,26 @@ int hermite_set_mixed_policy(hermite_ctx* c, int precision, double near_factor,
     drop_graphs(c);
     c->near_factor[precision] = near_factor;
     c->fp64_below[precision] = fp64_below;
+    return HERMITE_OK;
+}
+
+int hermite_set_mixed_small_blocks(hermite_ctx* c, int precision, int64_t fp64_inter_below)
+{
+    if (!c) return fail(HERMITE_EINVAL, "null context");
+    CHECK(check_precision(precision));
+    if (precision != HERMITE_MIXED && precision != HERMITE_MIXED_2F)
+        return fail(HERMITE_EINVAL, "only MIXED and MIXED_2F sweep small blocks in FP64");
+    if (fp64_inter_below < 0) return fail(HERMITE_EINVAL, "fp64_inter_below must be >= 0");
+    drop_graphs(c);
+    c->fp64_inter_below[precision] = fp64_inter_below;
+    return HERMITE_OK;
+}
+
+int hermite_get_mixed_small_blocks(hermite_ctx* c, int precision, int64_t* fp64_inter_below)
+{
+    if (!c || !fp64_inter_below) return fail(HERMITE_EINVAL, "null argument");
+    CHECK(check_precision(precision));
+    *fp64_inter_below = c->fp64_inter_below[precision];
     return HERMITE_OK;
 }
 

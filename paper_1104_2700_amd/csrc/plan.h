@@ -199,6 +199,7 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
             P->s_max = ch;
             P->jc = jc;
             P->total_items = tiles * ch;
+            P->fp64_all = (a.fp64_inter_below > 0 && (int64_t)na * a.n < a.fp64_inter_below) ? 1 : 0;
             if (a.counters && na > 0)
                 atomicAdd((unsigned long long*)&a.counters[1],
                           (unsigned long long)((int64_t)na * a.n));
@@ -307,6 +308,7 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         P->s_max = s_cmax[kWG - 1];
         P->jc = jc;
         P->total_items = s_items[kWG - 1];
+        P->fp64_all = (a.fp64_inter_below > 0 && s_inter[kWG - 1] < a.fp64_inter_below) ? 1 : 0;
         if (a.counters && s_inter[kWG - 1] > 0)
             atomicAdd((unsigned long long*)&a.counters[1],
                       (unsigned long long)s_inter[kWG - 1]);

@@ -796,7 +796,7 @@ sweep_kernel(SweepArgs a)
 
     SweepPlan* P = a.plan;
     const int tid = threadIdx.x;
-    int na, L, ti, s_max, total;
+    int na, L, ti, s_max, total, fp64_all = 0;
     int64_t jc, Tpred;
     const int32_t* idx_lds = nullptr;
     if constexpr (SEL) {
@@ -820,6 +820,7 @@ sweep_kernel(SweepArgs a)
                 P->s_max = s_max;
                 P->jc = jc;
                 P->total_items = total;
+                P->fp64_all = 0;
                 count_step(a.counters, Tpred, na);
                 if (a.counters && na > 0)
                     atomicAdd((unsigned long long*)&a.counters[1],
@@ -833,9 +834,15 @@ sweep_kernel(SweepArgs a)
         jc = P->jc;
         s_max = P->s_max;
         total = P->total_items;
+        fp64_all = P->fp64_all;
         Tpred = a.pred_x ? *a.pred_T : 0;
     }
     if (na == 0) return;
+    // a mixed sweep split over two launches (SweepArgs::kind): one system is
+    // all of one kind, so the other launch has nothing to do
+    if (a.kind != 0 && a.n_clusters == 1 &&
+        (fp64_all != 0 || a.n < a.fp64_below) != (a.kind == 2))
+        return;
     const int rows = kWG / L;          // lanes' slots per particle row
     const int slot = tid / L;
     const int sub = tid & (L - 1);
@@ -883,8 +890,9 @@ sweep_kernel(SweepArgs a)
             nf.near2f = (float)r2n;    // >= fl32(eps2): the self pair is always near
         }
         // a mixed sweep of an ensemble runs as two launches: this kernel
-        // takes the items of one kind of system only (see SweepArgs::kind)
-        if (a.kind != 0 && ((ce - cb) < a.fp64_below) != (a.kind == 2)) {
+        // takes the items of one kind only, FP64 for small systems and for
+        // small blocks (see SweepArgs::kind)
+        if (a.kind != 0 && (fp64_all != 0 || (ce - cb) < a.fp64_below) != (a.kind == 2)) {
             item += (int)gridDim.x;
             continue;
         }
@@ -1224,15 +1232,17 @@ void launch_sweep_kernels(SweepArgs a, int precision, int variant, int grid, boo
         hipLaunchKernelGGL(f, dim3(grid), dim3(kWG), 0, st, a);
     };
     const bool mixed = !pot_only && (precision == 1 || precision == 2);
+    const bool straddle = a.n_clusters > 1 && a.fp64_below > 1;
     if (!mixed) {
         go(precision, 0);
     } else if (a.n_cmax < a.fp64_below) {
         go(0, 0);                          // every system is small
-    } else if (a.n_clusters == 1 || a.fp64_below <= 1) {
-        go(precision, 0);                  // none is
-    } else {
+    } else if (straddle || (!sel && a.fp64_inter_below > 0)) {
+        // the plan decides on the device, per block, which items are FP64
         go(precision, 1);
         go(0, 2);
+    } else {
+        go(precision, 0);                  // no item is
     }
 }
 

@@ -89,6 +89,8 @@ _SIGS = {
     "hermite_get_tuning": ([_P, ctypes.c_int, _PT]),
     "hermite_set_mixed_policy": ([_P, ctypes.c_int, _d, _i64]),
     "hermite_get_mixed_policy": ([_P, ctypes.c_int, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
+    "hermite_set_mixed_small_blocks": ([_P, ctypes.c_int, _i64]),
+    "hermite_get_mixed_small_blocks": ([_P, ctypes.c_int, ctypes.POINTER(_i64)]),
     "hermite_set_tuning": ([_P, ctypes.c_int, _PT]),
     "hermite_autotune": ([_P, _PS, _PC, _d, ctypes.c_int, _i32, ctypes.c_char_p, _P]),
     "hermite_load_tuning": ([_P, ctypes.c_char_p, ctypes.c_int, _i64, _i32]),
@@ -382,6 +384,17 @@ class Context:
         _check(lib.hermite_get_mixed_policy(self.h, int(precision), ctypes.byref(f),
                                             ctypes.byref(b)), "hermite_get_mixed_policy")
         return f.value, b.value
+
+    def set_mixed_small_blocks(self, precision, fp64_inter_below):
+        _check(lib.hermite_set_mixed_small_blocks(self.h, int(precision), int(fp64_inter_below)),
+               "hermite_set_mixed_small_blocks")
+
+    def get_mixed_small_blocks(self, precision):
+        """Interactions below which a mixed sweep is done in FP64."""
+        b = _i64(0)
+        _check(lib.hermite_get_mixed_small_blocks(self.h, int(precision), ctypes.byref(b)),
+               "hermite_get_mixed_small_blocks")
+        return b.value
 
     def set_tuning(self, precision, tuning: CTuning):
         _check(lib.hermite_set_tuning(self.h, int(precision), ctypes.byref(tuning)),

@@ -54,11 +54,19 @@ TB = 20          # time tick 2^-20
 START_DIV = 0    # start-up factor = steady factor / START_DIV (0: the steady factor)
 FORMS = {"paper": H.DT_PAPER, "aarseth": H.DT_AARSETH}
 K_MIN, K_MAX = 3, 20
+RUN_FORM = H.DT_PAPER   # criterion form of the c1-c5 and e2 runs (the --form option)
+RUN_PREC = {}           # precision override of the c1-c5 runs (the --precision option)
 
 
-def _params(eta, form=H.DT_PAPER):
-    """Timestep parameters of the whole-run workloads (k in [3, 20]); the
-    start-up factor follows START_DIV (the --start-div option)."""
+def _prec(default):
+    return RUN_PREC.get("p", default)
+
+
+def _params(eta, form=None):
+    """Timestep parameters of the whole-run workloads (k in [K_MIN, K_MAX]);
+    the criterion form follows RUN_FORM and the start-up factor START_DIV
+    (the --form and --start-div options)."""
+    form = RUN_FORM if form is None else form
     eta_f = eta if form == H.DT_PAPER else math.sqrt(eta)
     return H.dt_params(eta, form, K_MIN, K_MAX,
                        eta_init=(eta_f / START_DIV) if START_DIV else 0.0)
@@ -73,10 +81,15 @@ def _energy(ctx, s, eps2, clusters=None):
     return e[:, 0] + e[:, 1]
 
 
+MAX_WALL = 0.0   # seconds; 0: no limit (the --max-wall option)
+
+
 def block_run(ctx, s, eps2, params, t_end, precision, clusters=None,
               chunk=20000, label=""):
     """Integrates an initialised state to t_end (time units), printing a
-    progress line every `chunk` launched steps.  Returns a dict of stats."""
+    progress line every `chunk` launched steps; with MAX_WALL set, stops
+    after the first chunk that ends past it (the stats then cover the time
+    reached, t_reached).  Returns a dict of stats."""
     T_end = int(round(t_end * (1 << TB)))
     e0 = _energy(ctx, s, eps2, clusters)
     c0 = ctx.counters()
@@ -84,6 +97,7 @@ def block_run(ctx, s, eps2, params, t_end, precision, clusters=None,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = inter = 0
+    t_reached = t_end
     while True:
         st, it, done = ctx.run(s, eps2, params, T_end, precision, use_graph=True,
                                sync_every=256, clusters=clusters, max_steps=chunk,
@@ -91,29 +105,56 @@ def block_run(ctx, s, eps2, params, t_end, precision, clusters=None,
         steps += st
         inter += it
         cnt = ctx.counters()
-        _log("  %s t = %.6f  block steps %d  interactions %.3e  %.1f s"
+        _log("  %s t = %.9f  block steps %d  interactions %.3e  %.1f s"
              % (label, cnt["T"] / (1 << TB), steps, inter, time.perf_counter() - t0))
         if done:
             break
+        if MAX_WALL and time.perf_counter() - t0 > MAX_WALL:
+            t_reached = cnt["T"] / (1 << TB)
+            break
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    e1 = _energy(ctx, s, eps2, clusters)
     c1 = ctx.counters()
     hist = (np.array(ctx.block_histogram()) - h0).tolist()
-    rel = np.abs((e1 - e0) / e0)
+    # a run stopped early has no synchronised state to take the energy of
+    rel = np.abs((_energy(ctx, s, eps2, clusters) - e0) / e0) if t_reached == t_end else None
     lv = TB - np.log2(s.dt.cpu().numpy()).astype(np.int64)
     return {
         "dt_levels_final": {int(k): int(c) for k, c in enumerate(np.bincount(lv)) if c},
-        "t_end": t_end, "wall_s": wall, "block_steps": steps, "interactions": inter,
+        "t_end": t_end, "t_reached": t_reached, "wall_s": wall, "block_steps": steps,
+        "interactions": inter,
         "interactions_per_s": inter / wall, "gflops_60": 60.0 * inter / wall / 1e9,
         "clamped_steps": c1["clamped"] - c0["clamped"],
-        "energy_rel_change_max": float(rel.max()),
-        "energy_rel_change_median": float(np.median(rel)),
+        "energy_rel_change_max": float(rel.max()) if rel is not None else None,
+        "energy_rel_change_median": float(np.median(rel)) if rel is not None else None,
         "E0": float(e0.sum()) if e0.size == 1 else None,
         "active_size_histogram_log2": {("0" if b == 0 else "[2^%d,2^%d)" % (b - 1, b)): v
                                        for b, v in enumerate(hist) if v},
         "mean_active": inter / max(steps, 1) / (s.n if clusters is None else 1),
     }
+
+
+class _fp32_mixed:
+    """Within the block, MIXED and MIXED_2F sweep every system and every
+    block with FP32 pair arithmetic (near field and refinement kept), as
+    the accuracy studies need; the policies are restored afterwards."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+
+    def __enter__(self):
+        self.saved = {p: (self.ctx.get_mixed_policy(p), self.ctx.get_mixed_small_blocks(p))
+                      for p in (H.MIXED, H.MIXED_2F)}
+        for p, ((near, _), _) in self.saved.items():
+            self.ctx.set_mixed_policy(p, near, 0)
+            self.ctx.set_mixed_small_blocks(p, 0)
+        return self
+
+    def __exit__(self, *exc):
+        for p, ((near, below), small) in self.saved.items():
+            self.ctx.set_mixed_policy(p, near, below)
+            self.ctx.set_mixed_small_blocks(p, small)
+        return False
 
 
 def sweep_time(ctx, s, eps2, precision, idx=None, reps=10):
@@ -159,7 +200,10 @@ def c2(ctx, t_end=1.0):
             "run": run}
 
 
-def c3(ctx, t_end=1.0):
+def c3(ctx, t_end=1.0, tune_cache=None, run=True):
+    """Sweep time against the active count (both precisions; with
+    tune_cache, each point at the launch shape the autotuner picks for that
+    count, kept in that cache), then a mixed-precision block run."""
     n = 65536
     s = _plummer_state(n, 3)
     eps2 = (4.0 / n) ** 2
@@ -167,20 +211,34 @@ def c3(ctx, t_end=1.0):
     s.vp.copy_(s.v)
     curve = []
     na = 1
+    saved = {p: ctx.get_tuning(H.PRECISIONS[p]) for p in ("fp64", "mixed")}
     while na <= n:
         idx = torch.arange(0, n, n // na, dtype=torch.int32, device="cuda")[:na].contiguous()
         row = {"n_act": na}
         for pname in ("fp64", "mixed"):
-            ms = sweep_time(ctx, s, eps2, H.PRECISIONS[pname], idx, reps=20)
+            prec = H.PRECISIONS[pname]
+            if tune_cache:
+                ctx.autotune(s, eps2, prec, na, cache_path=tune_cache)
+                row[pname + "_tuning"] = ctx.get_tuning(prec).as_dict()
+            ms = sweep_time(ctx, s, eps2, prec, idx, reps=20)
             row[pname + "_us"] = 1e3 * ms
             row[pname + "_interactions_per_s"] = na * n / (ms * 1e-3)
         curve.append(row)
         _log("  c3 n_act %6d  fp64 %.1f us  mixed %.1f us" % (na, row["fp64_us"], row["mixed_us"]))
         na *= 2
+    for pname, t in saved.items():
+        ctx.set_tuning(H.PRECISIONS[pname], t)
+    out = {"config": "plummer_n65536_mixed", "latency_curve": curve, "tuned": bool(tune_cache)}
+    if tune_cache:
+        with open(tune_cache) as f:
+            out["tuning_cache"] = json.load(f)
+    if not run:
+        return out
     p = _params(0.02)
-    ctx.initialize(s, eps2, p, H.MIXED)
-    run = block_run(ctx, s, eps2, p, t_end, H.MIXED, label="c3")
-    return {"config": "plummer_n65536_mixed", "latency_curve": curve, "run": run}
+    prec = _prec(H.MIXED)
+    ctx.initialize(s, eps2, p, prec)
+    out["run"] = block_run(ctx, s, eps2, p, t_end, prec, label="c3")
+    return out
 
 
 def c4(ctx, t_end=0.5, serial_t_end=0.125, n_clusters=256, serial_clusters=16):
@@ -196,9 +254,10 @@ def c4(ctx, t_end=0.5, serial_t_end=0.125, n_clusters=256, serial_clusters=16):
     s = H.State(x, v, m, TB)
     s.xp.copy_(s.x)
     s.vp.copy_(s.v)
-    out["tuning"] = ctx.autotune(s, 0.0, H.MIXED, int(off[-1]), clusters=cl).as_dict()
-    ctx.initialize(s, 0.0, p, H.MIXED, clusters=cl)
-    out["batched"] = block_run(ctx, s, 0.0, p, t_end, H.MIXED, clusters=cl, label="c4 batched")
+    prec = _prec(H.MIXED)
+    out["tuning"] = ctx.autotune(s, 0.0, prec, int(off[-1]), clusters=cl).as_dict()
+    ctx.initialize(s, 0.0, p, prec, clusters=cl)
+    out["batched"] = block_run(ctx, s, 0.0, p, t_end, prec, clusters=cl, label="c4 batched")
     # the same clusters, one system at a time, against the batched ensemble
     # of those clusters (a subset keeps the serial loop short)
     if serial_t_end and serial_clusters > 0:
@@ -239,28 +298,39 @@ def c5(ctx, t_end=0.25):
     s = H.State(x, v, m, TB)
     eps2 = 1e-5 ** 2
     p = _params(0.02)
-    ctx.initialize(s, eps2, p, H.MIXED_2F)
+    prec = _prec(H.MIXED_2F)
+    ctx.initialize(s, eps2, p, prec)
     return {"config": "plummer_imf_binaries_n131072_mixed2f",
-            "run": block_run(ctx, s, eps2, p, t_end, H.MIXED_2F, label="c5")}
+            "run": block_run(ctx, s, eps2, p, t_end, prec, label="c5")}
 
 
-def e3(ctx, t_end=0.375, etas=(0.0025, 0.005, 0.01, 0.02, 0.04, 0.08), n=1024, seed=1):
+def e3(ctx, t_end=0.375, etas=(0.0025, 0.005, 0.01, 0.02, 0.04, 0.08), n=1024, seed=1,
+       form="paper"):
     """Energy error against steps per crossing time (Section 4 energy study):
-    Plummer N = 1K, eps = 4/N, mixed and FP64 forces, several eta; the
-    error is averaged over the sync times 1/8, 2/8, 3/8 (potential energy
-    from FP64 sweeps); start-up factor eta/16.  n_step = particle steps per
-    particle per crossing time (2 sqrt 2 in N-body units)."""
+    Plummer N = 1K, eps = 4/N, FP64, mixed and FP32-jerk forces, several
+    eta, with the criterion as printed (form "paper": eta sqrt(R)) or in
+    its classic form ("aarseth": sqrt(eta R)); the error is averaged over
+    the sync times 1/8, 2/8, 3/8 (potential energy from FP64 sweeps);
+    start-up factor eta_f/16.  The mixed modes sweep this small system in
+    FP32 (the default policy would take FP64 below 8192 particles and for
+    blocks below 5e7 interactions): mixed with its FP64 near field and
+    refinement, mixed_sp as printed.  n_step =
+    particle steps per particle per crossing time (2 sqrt 2 in N-body
+    units)."""
     x, v, m = inputs.plummer(n, seed)
     eps2 = (4.0 / n) ** 2
     rows = []
+    dform = FORMS[form]
+    fp32 = _fp32_mixed(ctx).__enter__()
     for prec_name in ("fp64", "mixed", "mixed_sp"):
         prec = H.PRECISIONS[prec_name]
         for eta in etas:
             s = H.State(x, v, m, TB)
-            # start-up factor eta/16: with the steady factor the first step
+            # start-up factor eta_f/16: with the steady factor the first step
             # dominates the error over 3/8 time units (the scheme's error,
             # not the start-up, is what the study measures)
-            p = H.dt_params(eta, H.DT_PAPER, K_MIN, K_MAX, eta_init=eta / 16)
+            eta_f = eta if dform == H.DT_PAPER else math.sqrt(eta)
+            p = H.dt_params(eta, dform, K_MIN, K_MAX, eta_init=eta_f / 16)
             ctx.initialize(s, eps2, p, prec)
             e0 = _energy(ctx, s, eps2)[0]
             errs, inter, steps = [], 0, 0
@@ -281,18 +351,30 @@ def e3(ctx, t_end=0.375, etas=(0.0025, 0.005, 0.01, 0.02, 0.04, 0.08), n=1024, s
                          "mean_rel_energy_error": float(np.mean(errs)),
                          "rel_energy_error_at_sync": [float(e) for e in errs],
                          "block_steps": steps, "wall_s": wall, "dt_levels_final": levels})
-            _log("  e3 %-5s eta %.3f  n_step %8.1f  <|dE/E|> %.3e" %
-                 (prec_name, eta, n_step, np.mean(errs)))
+            _log("  e3 %-8s eta %.4f  n_step %9.1f  <|dE/E|> %.3e  %.1f s" %
+                 (prec_name, eta, n_step, np.mean(errs), wall))
     # slope of log error vs log n_step for FP64 over the converging part
     # (errors in [1e-13, 1e-6): larger ones leave the asymptotic regime,
     # smaller ones reach the FP64 rounding floor)
+    # (and per precision: the slope over its rows above 1e-9 and 4x its
+    # smallest error, i.e. before its floor, and that floor)
     f = [r for r in rows if r["precision"] == "fp64"
          and 1e-13 <= r["mean_rel_energy_error"] < 1e-6]
     ln = np.log([r["n_step"] for r in f])
     le = np.log([r["mean_rel_energy_error"] for r in f])
     slope = float(np.polyfit(ln, le, 1)[0]) if len(f) > 1 else None
-    return {"config": "energy_vs_nstep_plummer_n%d" % n, "t_end": t_end, "rows": rows,
-            "fp64_loglog_slope": slope}
+    per = {}
+    for prec_name in ("fp64", "mixed", "mixed_sp"):
+        rs = [r for r in rows if r["precision"] == prec_name]
+        floor = min(r["mean_rel_energy_error"] for r in rs)
+        fit = [r for r in rs if r["mean_rel_energy_error"] > max(1e-9, 4 * floor)]
+        sl = (float(np.polyfit(np.log([r["n_step"] for r in fit]),
+                               np.log([r["mean_rel_energy_error"] for r in fit]), 1)[0])
+              if len(fit) > 1 else None)
+        per[prec_name] = {"floor": floor, "slope_above_floor": sl, "rows_in_fit": len(fit)}
+    fp32.__exit__(None, None, None)
+    return {"config": "energy_vs_nstep_plummer_n%d" % n, "t_end": t_end, "form": form,
+            "rows": rows, "fp64_loglog_slope": slope, "per_precision": per}
 
 
 def e1(ctx, ns=(1024, 4096, 16384, 65536, 262144), sample=4096, seed=5):
@@ -302,7 +384,13 @@ def e1(ctx, ns=(1024, 4096, 16384, 65536, 262144), sample=4096, seed=5):
     index range; per-particle relative errors |f - f64| / |f64| of the
     acceleration and the jerk of each reduced-precision sweep against the
     FP64 sweep (median, 99th percentile, max), and the full-sweep time
-    (n_act = N) of every precision."""
+    (n_act = N) of every precision; the mixed precisions sweep every N
+    with FP32 pair arithmetic here."""
+    with _fp32_mixed(ctx):
+        return _e1(ctx, ns, sample, seed)
+
+
+def _e1(ctx, ns, sample, seed):
     rows = []
     for n in ns:
         x, v, m = inputs.plummer(n, seed)
@@ -337,16 +425,18 @@ def e1(ctx, ns=(1024, 4096, 16384, 65536, 262144), sample=4096, seed=5):
 
 def e2(ctx, t_end=0.125, n=262144, seed=6):
     """Block runs with FP64 (mixed) and FP32 (mixed_sp) jerk sums side by
-    side: the paper finds no difference in energy conservation (Section 4)."""
+    side: the paper finds no difference in energy conservation (Section 4).
+    Both sweep every block with FP32 pair arithmetic."""
     x, v, m = inputs.plummer(n, seed)
     eps2 = (4.0 / n) ** 2
     p = _params(0.02)
     out = {"config": "plummer_n%d_jerk_sum_precision" % n, "t_end": t_end, "runs": {}}
-    for pname in ("mixed", "mixed_sp"):
-        s = H.State(x, v, m, TB)
-        ctx.initialize(s, eps2, p, H.PRECISIONS[pname])
-        out["runs"][pname] = block_run(ctx, s, eps2, p, t_end, H.PRECISIONS[pname],
-                                       label="e2 " + pname)
+    with _fp32_mixed(ctx):
+        for pname in ("mixed", "mixed_sp"):
+            s = H.State(x, v, m, TB)
+            ctx.initialize(s, eps2, p, H.PRECISIONS[pname])
+            out["runs"][pname] = block_run(ctx, s, eps2, p, t_end, H.PRECISIONS[pname],
+                                           label="e2 " + pname)
     return out
 
 
@@ -446,36 +536,73 @@ def main(argv=None):
     ap.add_argument("--serial-t-end", type=float, default=None)
     ap.add_argument("--serial-clusters", type=int, default=None)
     ap.add_argument("--form", choices=sorted(FORMS), default=None,
-                    help="timestep criterion form (e4 only)")
+                    help="timestep criterion form (default: as printed)")
     ap.add_argument("--start-div", type=float, default=0.0,
                     help="start-up factor = steady factor / this (0: the steady factor)")
     ap.add_argument("--tick-bits", type=int, default=None,
                     help="time tick 2^-tick_bits (default 20)")
+    ap.add_argument("--k-min", type=int, default=None,
+                    help="coarsest step 2^-k_min (default 3; a run ends on its multiple)")
     ap.add_argument("--k-max", type=int, default=None,
                     help="finest step 2^-k_max (default 20; at most tick_bits)")
+    ap.add_argument("--max-wall", type=float, default=0.0,
+                    help="stop a block run after this many seconds (0: run to the end)")
+    ap.add_argument("--precision", choices=sorted(H.PRECISIONS), default=None,
+                    help="c3, c4, c5: run in this precision instead of the configured one")
+    ap.add_argument("--fp64-below", type=int, default=None,
+                    help="mixed precisions: sweep systems below this size in FP64 "
+                         "(library default 8192; 0: every system in FP32)")
+    ap.add_argument("--small-blocks", type=int, default=None,
+                    help="mixed precisions: blocks below this many interactions are swept "
+                         "in FP64 (library default 5e7; 0: never)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="c3: autotune every point of the latency curve into this cache")
+    ap.add_argument("--no-run", action="store_true", help="c3: the latency curve only")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    global START_DIV, TB, K_MAX
+    global START_DIV, TB, K_MIN, K_MAX, MAX_WALL, RUN_FORM
     START_DIV = a.start_div
+    MAX_WALL = a.max_wall
     if a.tick_bits is not None:
         TB = a.tick_bits
     if a.k_max is not None:
         K_MAX = a.k_max
+    if a.k_min is not None:
+        K_MIN = a.k_min
     ctx = H.Context(0)
+    if a.precision is not None:
+        RUN_PREC["p"] = H.PRECISIONS[a.precision]
+    if a.small_blocks is not None:
+        for prec in (H.MIXED, H.MIXED_2F):
+            ctx.set_mixed_small_blocks(prec, a.small_blocks)
+    if a.fp64_below is not None:
+        for prec in (H.MIXED, H.MIXED_2F):
+            near, _ = ctx.get_mixed_policy(prec)
+            ctx.set_mixed_policy(prec, near, a.fp64_below)
     kw = {}
     if a.t_end is not None:
         kw["t_end"] = a.t_end
+    if a.name == "c3" and a.tune_cache:
+        kw["tune_cache"] = a.tune_cache
+    if a.name == "c3" and a.no_run:
+        kw["run"] = False
     if a.name == "c4" and a.serial_t_end is not None:
         kw["serial_t_end"] = a.serial_t_end
     if a.name == "c4" and a.serial_clusters is not None:
         kw["serial_clusters"] = a.serial_clusters
-    if a.name == "e4" and a.form is not None:
+    if a.name in ("e3", "e4") and a.form is not None:
         kw["form"] = a.form
+    elif a.form is not None:
+        RUN_FORM = FORMS[a.form]
     _log("workload %s %s" % (a.name, kw))
     res = RUNNERS[a.name](ctx, **kw)
     res["device"] = torch.cuda.get_device_name(0)
     res["start_div"] = START_DIV
     res["tick_bits"] = TB
+    res["criterion_form"] = "paper" if RUN_FORM == H.DT_PAPER else "aarseth"
+    res["mixed_policy"] = list(ctx.get_mixed_policy(H.MIXED)) + [
+        ctx.get_mixed_small_blocks(H.MIXED)]
+    res["precision_override"] = a.precision
     res["k_min_max"] = [K_MIN, K_MAX]
     txt = json.dumps(res)
     if a.out:

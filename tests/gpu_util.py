@@ -55,18 +55,22 @@ def check_mixed(name, got, ref, cond, tol=TOL_MIXED, cond_factor=4.0, max_second
 
 
 def fp32_policy(H, ctx, near_factor=3.0):
-    """Makes the mixed precisions sweep every system in FP32 (with their
-    near field and refinement), as they do for N >= 8192 by default; returns
-    the previous policies for restore_policy."""
-    saved = {p: ctx.get_mixed_policy(p) for p in (H.MIXED, H.MIXED_2F)}
+    """Makes the mixed precisions sweep every system and every block in
+    FP32 (with their near field and refinement), as they do by default for
+    N >= 8192 and blocks of at least 5e7 interactions; returns the previous
+    policies for restore_policy."""
+    saved = {p: (ctx.get_mixed_policy(p), ctx.get_mixed_small_blocks(p))
+             for p in (H.MIXED, H.MIXED_2F)}
     for p in (H.MIXED, H.MIXED_2F):
         ctx.set_mixed_policy(p, near_factor, 0)
+        ctx.set_mixed_small_blocks(p, 0)
     return saved
 
 
 def restore_policy(ctx, saved):
-    for p, (f, b) in saved.items():
+    for p, ((f, b), sb) in saved.items():
         ctx.set_mixed_policy(p, f, b)
+        ctx.set_mixed_small_blocks(p, sb)
 
 
 def plummer_state(n, seed):

@@ -235,6 +235,40 @@ def test_lockstep_block_steps(H, ctx, prec):
         restore_policy(ctx, saved)
 
 
+def test_mixed_small_block_steps_take_fp64(H, ctx):
+    """Block steps with the default mixed policy: while a block's sweep is
+    below 5e7 interactions it is done in FP64 (with the mixed path's
+    flagging reduce and corrector), so the state follows FP64 steps bit for
+    bit; hermite_run and hermite_step agree too."""
+    n = 20000
+    x, v, m, _ = _c1_setup(H, n=n, seed=51)
+    eps2 = (4.0 / n) ** 2
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, eps2, params, H.FP64)
+    sa, sb = s0.clone(), s0.clone()
+    checked = 0
+    for k in range(16):
+        ctx.step(sa, eps2, params, H.FP64)
+        na = ctx.counters()["n_act"]
+        ctx.step(sb, eps2, params, H.MIXED)
+        torch.cuda.synchronize()
+        if na * n >= 50000000:
+            break
+        for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+            assert torch.equal(getattr(sa, key), getattr(sb, key)), (k, key)
+        checked += 1
+    assert checked >= 8
+    sc = s0.clone()
+    ctx.run(sc, eps2, params, 1 << (TB - 3), H.MIXED, max_steps=checked)
+    sd = s0.clone()
+    for k in range(checked):
+        ctx.step(sd, eps2, params, H.FP64)
+    torch.cuda.synchronize()
+    for key in ("x", "v", "a", "j", "pot", "t", "dt"):
+        assert torch.equal(getattr(sc, key), getattr(sd, key)), key
+
+
 @pytest.mark.parametrize("n", [3, 3000, 6000, 20000])
 def test_lockstep_larger_systems(H, ctx, n):
     """Block steps of systems on each selection path: selection fused into

@@ -168,6 +168,40 @@ def test_mixed_small_systems_take_fp64(H, ctx):
     assert ctx.get_mixed_policy(H.MIXED) == (3.0, 8192)
 
 
+def test_mixed_small_blocks_take_fp64(H, ctx):
+    """Default policy: a mixed sweep of fewer than 5e7 interactions is done
+    by the FP64 kernel (decided on the device from the active count), so it
+    equals the FP64 sweep bit for bit at the same launch shape; a larger one
+    uses FP32 pair arithmetic and meets the mixed bar; the setting is
+    validated."""
+    from oracle import oracle as O
+    assert ctx.get_mixed_small_blocks(H.MIXED) == 50000000
+    assert ctx.get_mixed_small_blocks(H.MIXED_2F) == 50000000
+    assert ctx.get_mixed_small_blocks(H.MIXED_SP) == 0
+    n = 20000
+    s, x, v, m = _state(H, n, 13)
+    eps2 = (4.0 / n) ** 2
+    for n_act, small in ((64, True), (2400, True), (4000, False)):
+        idx = _idx(n, n_act, 77)
+        ti = torch.from_numpy(idx).cuda()
+        ref = ctx.force_jerk(s, ti, eps2, H.FP64)
+        for prec in (H.MIXED, H.MIXED_2F):
+            got = ctx.force_jerk(s, ti, eps2, prec)
+            torch.cuda.synchronize()
+            same = all(torch.equal(got[q], ref[q]) for q in range(3))
+            assert same == small, (n_act, prec)
+            if not small:
+                ra, rj, rp, cond = O.force(x, v, m, idx[:300], eps2, with_cond=True)
+                check_mixed("acc", got[0].cpu().numpy()[:, :300], ra, cond[0])
+                check_mixed("jerk", got[1].cpu().numpy()[:, :300], rj, cond[1])
+                check_mixed("pot", got[2].cpu().numpy()[None, :300], rp[None], cond[2])
+    for args in ((H.FP64, 0), (H.MIXED_SP, 10), (H.MIXED, -1)):
+        with pytest.raises(H.HermiteError) as err:
+            ctx.set_mixed_small_blocks(*args)
+        assert err.value.code == H.EINVAL
+    assert ctx.get_mixed_small_blocks(H.MIXED) == 50000000
+
+
 def test_mixed_ensemble_straddling_threshold(H, ctx):
     """An ensemble whose clusters straddle fp64_below runs two kernels:
     the small clusters' sums equal the FP64 sweep's bit for bit, the large
