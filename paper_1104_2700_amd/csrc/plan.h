@@ -169,13 +169,61 @@ __host__ __device__ inline void plan_split(const SweepArgs& a, int32_t na, int64
     *jc_out = jc;
 }
 
+__device__ inline int32_t block_exscan(int32_t v, int32_t* total)
+{
+    __shared__ int32_t s_w[kWG / 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    int32_t off = x - v, tot = 0;
+    for (int w = 0; w < kWG / 64; ++w) {
+        off += w < wave ? s_w[w] : 0;
+        tot += s_w[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off;
+}
+
+// Block-wide (kWG threads) sum of an int64 and maximum of an int32, by
+// wave shuffles and one round through LDS; every thread calls it and gets
+// both results.
+__device__ inline void block_sum_max(int64_t* sum, int32_t* mx)
+{
+    __shared__ int64_t s_s[kWG / 64];
+    __shared__ int32_t s_m[kWG / 64];
+    int64_t v = *sum;
+    int32_t m = *mx;
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_xor(v, o);
+        const int32_t u = __shfl_xor(m, o);
+        m = u > m ? u : m;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_s[wave] = v;
+        s_m[wave] = m;
+    }
+    __syncthreads();
+    v = 0;
+    m = s_m[0];
+    for (int w = 0; w < kWG / 64; ++w) {
+        v += s_s[w];
+        m = s_m[w] > m ? s_m[w] : m;
+    }
+    __syncthreads();
+    *sum = v;
+    *mx = m;
+}
+
 __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
 {
-    __shared__ int32_t s_items[kWG];
-    __shared__ int32_t s_cmax[kWG];
-    __shared__ int64_t s_inter[kWG];
-    __shared__ int32_t s_L, s_ti;
-    __shared__ int64_t s_jc;
     const int tid = threadIdx.x;
     const int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
     const int C = a.n_clusters;
@@ -246,23 +294,14 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         a.act_cnt[c] = cnt;
         nact_c += cnt > 0 ? 1 : 0;
     }
-    s_items[tid] = nact_c;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if (tid < s) s_items[tid] += s_items[tid + s];
-        __syncthreads();
-    }
+    int32_t c_act;
+    (void)block_exscan(nact_c, &c_act);
 
-    // 2. the split: lanes per particle L and chunk length jc
-    if (tid == 0) {
-        int32_t L, ti_l;
-        int64_t jc;
-        plan_split(a, na, s_items[0] > 0 ? s_items[0] : 1, &L, &ti_l, &jc);
-        s_L = L; s_ti = ti_l; s_jc = jc;
-    }
-    __syncthreads();
-    const int32_t ti = s_ti;
-    const int64_t jc = s_jc;
+    // 2. the split: lanes per particle L and chunk length jc (every thread
+    // evaluates it; it depends only on na, c_act and the arguments)
+    int32_t L, ti;
+    int64_t jc;
+    plan_split(a, na, c_act > 0 ? c_act : 1, &L, &ti, &jc);
 
     // 3. work items per cluster and their offsets
     int32_t local = 0, cmax = 0;
@@ -278,40 +317,25 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
         cmax = ch > cmax ? ch : cmax;
         inter += (int64_t)cnt * (o1 - o0);
     }
-    __syncthreads();
-    s_items[tid] = local;
-    s_cmax[tid] = cmax;
-    s_inter[tid] = inter;
-    __syncthreads();
-    // inclusive scan of item counts (Hillis-Steele), max and sum
-    for (int d = 1; d < kWG; d <<= 1) {
-        int32_t v = tid >= d ? s_items[tid - d] : 0;
-        int32_t mx = tid >= d ? s_cmax[tid - d] : 0;
-        int64_t iv = tid >= d ? s_inter[tid - d] : 0;
-        __syncthreads();
-        s_items[tid] += v;
-        s_cmax[tid] = mx > s_cmax[tid] ? mx : s_cmax[tid];
-        s_inter[tid] += iv;
-        __syncthreads();
-    }
-    int32_t base = tid > 0 ? s_items[tid - 1] : 0;
+    int32_t total;
+    int32_t base = block_exscan(local, &total);
+    block_sum_max(&inter, &cmax);
     for (int c = c0; c < c1; ++c) {
         a.item_off[c] = base;
         base += ((a.act_cnt[c] + ti - 1) / ti) * a.chunks[c];
     }
-    if (tid == kWG - 1) {
-        a.item_off[C] = s_items[kWG - 1];
+    if (tid == 0) {
+        a.item_off[C] = total;
         SweepPlan* P = a.plan;
         P->n_act = na;
-        P->L = s_L;
+        P->L = L;
         P->ti = ti;
-        P->s_max = s_cmax[kWG - 1];
+        P->s_max = cmax;
         P->jc = jc;
-        P->total_items = s_items[kWG - 1];
-        P->fp64_all = (a.fp64_inter_below > 0 && s_inter[kWG - 1] < a.fp64_inter_below) ? 1 : 0;
-        if (a.counters && s_inter[kWG - 1] > 0)
-            atomicAdd((unsigned long long*)&a.counters[1],
-                      (unsigned long long)s_inter[kWG - 1]);
+        P->total_items = total;
+        P->fp64_all = (a.fp64_inter_below > 0 && inter < a.fp64_inter_below) ? 1 : 0;
+        if (a.counters && inter > 0)
+            atomicAdd((unsigned long long*)&a.counters[1], (unsigned long long)inter);
     }
 }
 
@@ -471,28 +495,6 @@ __device__ inline bool needs_refine(const SweepArgs& a, const double s[kRows])
 
 // Exclusive scan of one value per thread over the workgroup (all kWG
 // threads call it); *total receives the sum.
-__device__ inline int32_t block_exscan(int32_t v, int32_t* total)
-{
-    __shared__ int32_t s_w[kWG / 64];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
-    if (lane == 63) s_w[wave] = x;
-    __syncthreads();
-    int32_t off = x - v, tot = 0;
-    for (int w = 0; w < kWG / 64; ++w) {
-        off += w < wave ? s_w[w] : 0;
-        tot += s_w[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return off;
-}
-
 // The flagging reduce handles the active positions in units: one round of
 // a workgroup, kWG positions (a thread each) or kWG / 64 (a wave each).
 // Every thread of the workgroup calls this once per round, with its flag
