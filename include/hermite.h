@@ -296,14 +296,15 @@ int hermite_step(hermite_ctx* ctx, const hermite_state* s,
  * is due before the latest t, the next block time is the first multiple of
  * the smallest occupied step after the last block time and the active
  * block is a prefix of that order, so each step selects in O(n_act) (one
- * kernel) instead of scanning t and dt; otherwise, and for one system of
+ * kernel; for clusters, each cluster keeps its own order and two kernels
+ * re-sort and list the clusters' prefixes, with no workgroup waiting on
+ * another) instead of scanning t and dt; otherwise, and for one system of
  * n <= 2048 (selected inside the sweep) or more than 2048 clusters, the
  * run selects as hermite_step does.  Both give the same state bit for bit.
- * With clusters, large blocks are shared by 16 workgroups that wait for
- * each other with bounded waits; should a wait run out (the workgroups
- * could not run at the same time, e.g. a device filled by other work), the
- * call returns HERMITE_EHIP with a message and the state is not to be
- * trusted.
+ * Should the order ever be inconsistent (a position out of range, which a
+ * state left as the scheme produces it cannot give), the call returns
+ * HERMITE_EHIP with a message instead of writing out of range, and the
+ * state is not to be trusted.
  *
  * steps_out / interactions_out (host, may be NULL) receive the block-step
  * count and the number of pair interactions (sum over steps of

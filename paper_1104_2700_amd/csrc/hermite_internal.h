@@ -243,7 +243,7 @@ struct LevelArgs {
     int64_t dt_floor;    // smallest step the corrector can give, 2^(tick_bits - k_max)
     int32_t* perm;       // [n] particle ids by step size, smallest first (ensembles:
                          // within each cluster's range)
-    int32_t* cnt;        // [64] particles with dt = 2^b ticks (one system)
+    int32_t* cnt;        // [64] particles with dt = 2^b ticks (of the whole ensemble)
     int32_t* cursor;     // [64] (building the order)
     int64_t* misc;       // [0] T_last; [1] max t, [2] min t + dt, [3] inconsistent (checks);
                          // [4] a position out of range was not written
@@ -260,7 +260,6 @@ struct LevelArgs {
     const int64_t* offsets;  // [C + 1]
     int32_t* ccnt;       // [C][64] particles of cluster c with dt = 2^b ticks
     int32_t* ccum;       // [C][64] their running sums over b (steps <= 2^b)
-    int32_t* cmin;       // [C] smallest occupied b of cluster c (64: none)
     int32_t* cna;        // [C] size of cluster c's last block
 };
 

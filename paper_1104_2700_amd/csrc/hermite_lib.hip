@@ -84,7 +84,7 @@ struct hermite_ctx {
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
     Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_na, lvl_bits;
-    Buf lvl_ccnt, lvl_ccum, lvl_cmin, lvl_cna;   // ensembles: per-cluster orders
+    Buf lvl_ccnt, lvl_ccum, lvl_cna;   // ensembles: per-cluster orders
     std::vector<GraphEntry> graphs;
     // grid of the fused select + sweep for the last shape it was sized for
     struct {
@@ -487,7 +487,6 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_clust
         L.offsets = cl->offsets;
         L.ccnt = (int32_t*)c->lvl_ccnt.p;
         L.ccum = (int32_t*)c->lvl_ccum.p;
-        L.cmin = (int32_t*)c->lvl_cmin.p;
         L.cna = (int32_t*)c->lvl_cna.p;
     }
     return L;
@@ -512,7 +511,6 @@ int level_init(hermite_ctx* c, const hermite_state* s, const hermite_clusters* c
         const size_t C = (size_t)cl->n_clusters;
         CHECK(ensure(c, c->lvl_ccnt, sizeof(int32_t) * 64 * C));
         CHECK(ensure(c, c->lvl_ccum, sizeof(int32_t) * 64 * C));
-        CHECK(ensure(c, c->lvl_cmin, sizeof(int32_t) * C));
         CHECK(ensure(c, c->lvl_cna, sizeof(int32_t) * C));
     }
     const LevelArgs L = level_args(c, s, cl, p, 0);
@@ -823,7 +821,7 @@ int hermite_destroy(hermite_ctx* c)
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
                    &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
                    &c->lvl_cursor, &c->lvl_misc, &c->lvl_na, &c->lvl_ccnt, &c->lvl_ccum,
-                   &c->lvl_cmin, &c->lvl_cna,
+                   &c->lvl_cna,
                    &c->lvl_bits};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);

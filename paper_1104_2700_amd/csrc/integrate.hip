@@ -683,9 +683,10 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
 }
 
 // Ensembles.  Cluster c keeps its own step-size order in its range of perm,
-// perm[off_c, off_c+1), with its step counts ccnt[c][b], their running sums
-// ccum[c][b] and its smallest occupied step cmin[c]; all clusters share the
-// block time, and cluster c's part of a block is a prefix of its range.
+// perm[off_c, off_c+1), with its step counts ccnt[c][b] and their running
+// sums ccum[c][b]; cnt[b] holds the counts of the whole ensemble.  All
+// clusters share the block time, and cluster c's part of a block is a
+// prefix of its range.
 
 // Builds every cluster's order from t and dt (one workgroup per cluster).
 __global__ void __launch_bounds__(kWG) cl_build_kernel(LevelArgs L)
@@ -703,11 +704,7 @@ __global__ void __launch_bounds__(kWG) cl_build_kernel(LevelArgs L)
         base[tid] = x - k;
         L.ccnt[c * 64 + tid] = k;
         L.ccum[c * 64 + tid] = x;
-        const unsigned long long occ = __ballot(k > 0);
-        if (tid == 0) {
-            L.cmin[c] = occ ? __builtin_ctzll(occ) : 64;
-            L.cna[c] = 0;
-        }
+        if (tid == 0) L.cna[c] = 0;
     }
     __syncthreads();
     for (int64_t i = o0 + tid; i < o1; i += kWG) {
@@ -722,30 +719,33 @@ __global__ void __launch_bounds__(kWG) cl_build_kernel(LevelArgs L)
 }
 
 // Re-sorts every cluster's part of the last block by its new steps: one
-// workgroup per cluster, each on its own range.
+// workgroup per cluster, each on its own range; the ensemble's counts take
+// each cluster's changes (integer atomics, so their sum is exact).
 __global__ void __launch_bounds__(kWG) cl_resort_kernel(LevelArgs L)
 {
     __shared__ LevelLds S;
     const int tid = threadIdx.x, c = blockIdx.x;
-    if (*L.na_prev <= 0) return;
+    // every load this workgroup may need is issued before any is waited on
+    const int32_t na_prev = *L.na_prev;
     const int64_t T_prev = *L.T;
-    if (c == 0 && tid == 0) L.misc[0] = T_prev;
     const int32_t m = L.cna[c];
+    const int64_t o = L.offsets[c], o1 = L.offsets[c + 1];
+    const int32_t old = tid < 64 ? L.ccnt[c * 64 + tid] : 0;
+    if (na_prev <= 0) return;
+    if (c == 0 && tid == 0) L.misc[0] = T_prev;
     if (m <= 0) return;
-    const int64_t o = L.offsets[c];
-    if ((int64_t)m > L.offsets[c + 1] - o) {
+    if ((int64_t)m > o1 - o) {
         if (tid == 0)
             __hip_atomic_store(&L.misc[4], (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    if (tid < 64) S.cnt[tid] = L.ccnt[c * 64 + tid];
+    if (tid < 64) S.cnt[tid] = old;
     level_resort(L, L.perm + o, L.tmp + o, m, __builtin_ctzll((unsigned long long)T_prev), S);
     if (tid < 64) {
         const int32_t k = S.cnt[tid];
         L.ccnt[c * 64 + tid] = k;
         L.ccum[c * 64 + tid] = wave_inscan_i32(k);
-        const unsigned long long occ = __ballot(k > 0);
-        if (tid == 0) L.cmin[c] = occ ? __builtin_ctzll(occ) : 64;
+        if (k != old) atomicAdd(&L.cnt[tid], k - old);
     }
 }
 
@@ -758,17 +758,18 @@ __global__ void __launch_bounds__(kWG) cl_resort_kernel(LevelArgs L)
 __global__ void __launch_bounds__(kWG) cl_select_kernel(LevelArgs L, SweepArgs sa)
 {
     __shared__ int32_t s_start[kLdsClusters + 1];
-    __shared__ int64_t s_min[kWG / 64];
     __shared__ int32_t s_scan[kWG / 64];
+    __shared__ int32_t s_bm;
     const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
     const int C = L.n_clusters;
     const int64_t Tlast = L.misc[0];
-    int64_t bm = 64;
-    for (int c = tid; c < C; c += kWG) {
-        const int64_t v = L.cmin[c];
-        bm = v < bm ? v : bm;
+    // the smallest occupied step of the ensemble (one lane per step size)
+    if (tid < 64) {
+        const unsigned long long occ = __ballot(L.cnt[tid] > 0);
+        if (tid == 0) s_bm = occ ? __builtin_ctzll(occ) : 64;
     }
-    bm = block_min_i64(bm, s_min);
+    __syncthreads();
+    const int bm = s_bm;
     int64_t Tn = INT64_MAX;
     int zn = -1;
     if (bm < 64) {

@@ -838,11 +838,16 @@ sweep_kernel(SweepArgs a)
         Tpred = a.pred_x ? *a.pred_T : 0;
     }
     if (na == 0) return;
-    // a mixed sweep split over two launches (SweepArgs::kind): one system is
-    // all of one kind, so the other launch has nothing to do
-    if (a.kind != 0 && a.n_clusters == 1 &&
-        (fp64_all != 0 || a.n < a.fp64_below) != (a.kind == 2))
-        return;
+    // a mixed sweep split over two launches (SweepArgs::kind): a launch with
+    // no item of its kind leaves at once (one system is all of one kind; an
+    // FP64 block is all FP64; with no small systems only such a block has
+    // FP64 items)
+    if (a.kind != 0) {
+        const bool all64 = fp64_all != 0 || (a.n_clusters == 1 && a.n < a.fp64_below);
+        const bool none64 = fp64_all == 0 && (a.n_clusters == 1 ? a.n >= a.fp64_below
+                                                                 : a.fp64_below <= 1);
+        if ((a.kind == 1 && all64) || (a.kind == 2 && none64)) return;
+    }
     const int rows = kWG / L;          // lanes' slots per particle row
     const int slot = tid / L;
     const int sub = tid & (L - 1);

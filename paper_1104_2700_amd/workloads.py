@@ -552,6 +552,8 @@ def main(argv=None):
     ap.add_argument("--fp64-below", type=int, default=None,
                     help="mixed precisions: sweep systems below this size in FP64 "
                          "(library default 8192; 0: every system in FP32)")
+    ap.add_argument("--etas", default=None,
+                    help="e3: comma-separated eta values (default 0.0025 .. 0.08)")
     ap.add_argument("--small-blocks", type=int, default=None,
                     help="mixed precisions: blocks below this many interactions are swept "
                          "in FP64 (library default 5e7; 0: never)")
@@ -590,6 +592,8 @@ def main(argv=None):
         kw["serial_t_end"] = a.serial_t_end
     if a.name == "c4" and a.serial_clusters is not None:
         kw["serial_clusters"] = a.serial_clusters
+    if a.name == "e3" and a.etas:
+        kw["etas"] = tuple(float(e) for e in a.etas.split(","))
     if a.name in ("e3", "e4") and a.form is not None:
         kw["form"] = a.form
     elif a.form is not None:

@@ -131,12 +131,13 @@ def _levels(dt):
                           (13, [90, 400, 3, 250], 6, 32, 40)])
 def test_ensemble_orders_per_cluster(seed, sizes, k_min, k_max, tb):
     """The ensemble form: each cluster keeps its own order in its range of
-    the permutation, its step counts, their running sums and its smallest
-    occupied step.  Each step every cluster re-sorts only its part of the
-    last block; the selection takes the block time from the smallest
-    occupied step over all clusters and cluster c's part as the prefix of
-    its range given by its running sum at the block time's level, listed
-    at the exclusive scan of those counts.  Checked against the oracle's
+    the permutation, its step counts and their running sums; the ensemble's
+    counts are kept by adding each re-sorted cluster's changes.  Each step
+    every cluster re-sorts only its part of the last block; the selection
+    takes the block time from the smallest occupied step of the ensemble's
+    counts and cluster c's part as the prefix of its range given by its
+    running sum at the block time's level, listed at the exclusive scan of
+    those counts.  Checked against the oracle's
     selection over the whole ensemble, with every list position in range
     and every cluster's order sorted, through steps of a deep hierarchy
     (tick_bits 40, k_max 32) too."""
@@ -154,7 +155,7 @@ def test_ensemble_orders_per_cluster(seed, sizes, k_min, k_max, tb):
         perm[off[c]:off[c + 1]] = r[np.argsort(b[r], kind="stable")]
         ccnt[c] = np.bincount(b[r], minlength=64)
     ccum = np.cumsum(ccnt, axis=1)
-    cmin = np.array([np.nonzero(ccnt[c])[0][0] if ccnt[c].any() else 64 for c in range(C)])
+    gcnt = np.bincount(b, minlength=64)      # the ensemble's counts
     cna = np.zeros(C, dtype=np.int64)
     T_last, na_prev, T_prev = int(t.max()), 0, 0
     for _ in range(300):
@@ -171,19 +172,20 @@ def test_ensemble_orders_per_cluster(seed, sizes, k_min, k_max, tb):
                 nb = _levels(dt[blk])
                 assert nb.max() <= z
                 perm[off[c]:off[c] + m] = blk[np.argsort(nb, kind="stable")]
+                old = ccnt[c].copy()
                 ccnt[c, :z + 1] = 0
                 ccnt[c] += np.bincount(nb, minlength=64)
                 ccum[c] = np.cumsum(ccnt[c])
-                occ = np.nonzero(ccnt[c])[0]
-                cmin[c] = occ[0] if occ.size else 64
+                gcnt += ccnt[c] - old
         bl = _levels(dt)
         for c in range(C):
             seg = bl[perm[off[c]:off[c + 1]]]
             assert np.all(np.diff(seg) >= 0)
             assert np.array_equal(ccnt[c], np.bincount(bl[off[c]:off[c + 1]], minlength=64))
             assert np.array_equal(np.sort(perm[off[c]:off[c + 1]]), np.arange(off[c], off[c + 1]))
+        assert np.array_equal(gcnt, np.bincount(bl, minlength=64))
         # selection: block time, per-cluster counts and first positions
-        bm = int(cmin.min())
+        bm = int(np.nonzero(gcnt)[0][0])
         T = ((T_last >> bm) + 1) << bm
         zn = (T & -T).bit_length() - 1
         counts = ccum[:, zn]
