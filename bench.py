@@ -16,7 +16,9 @@ the FP64 refinement of the particles whose FP32 rounding estimate exceeds
 the bound, so that every particle meets 1e-6 (the count refined per step is
 reported).  The roofline entry is for the sweep kernel (the dominant
 kernel), with its average duration measured by HIP events recorded on the
-launch stream around that kernel alone, priced at 42 algorithmic flops per
+launch stream around the sweep launches alone (the mixed sweep is launched
+with its FP64 half, which leaves at once for a full-N block and takes a few
+microseconds), priced at 42 algorithmic flops per
 interaction (count of the operations in the force, jerk and potential
 equations, FMA = 2); the whole force call (plan, sweep, reduce/refine) is
 reported beside it.  Both FP32 difference forms of the mixed sweep (cast and

@@ -361,7 +361,7 @@ int hermite_get_tuning(hermite_ctx* ctx, int precision, hermite_tuning* out);
  * the estimate exceeds 4e-8 of its acceleration or jerk: particles whose
  * sums almost cancel.  The count is reported by hermite_counters.
  *
- * Defaults: near_factor 3, fp64_below 8192 for HERMITE_MIXED and
+ * Defaults: near_factor 3, fp64_below 32768 for HERMITE_MIXED and
  * HERMITE_MIXED_2F; 0 and 0 for HERMITE_MIXED_SP (the scheme as printed).
  * EINVAL for HERMITE_FP64, a negative, infinite or NaN near_factor, a
  * negative fp64_below, or fp64_below != 0 for HERMITE_MIXED_SP.  Setting

@@ -210,10 +210,13 @@ hermite_tuning default_tuning(const hermite_ctx* c, int precision)
 // core in standard units): the FP32 pair error of a particle is led by its
 // nearest pairs, whose terms are the largest, so HERMITE_MIXED and
 // HERMITE_MIXED_2F sum the pairs within this radius in FP64.  Systems
-// smaller than fp64_below are swept in FP64 altogether: below about 10^4
-// particles the FP64 sweep takes no longer than the FP32 one with its near
-// field (MI355X: 0.020 / 0.020 ms at N = 1024, 0.042 / 0.049 ms at 4096,
-// 0.33 / 0.32-0.36 ms at 16384; 5.1 / 4.0 ms at 65536).  The paper-faithful
+// smaller than fp64_below are swept in FP64 altogether: up to about 2^15
+// particles the FP64 sweep of all of them takes no longer than the FP32 one
+// with its near field and refinement (MI355X, default launch shapes: FP64 /
+// mixed 0.019 / 0.042 ms at N = 1024, 0.044 / 0.074 at 4096, 0.364 / 0.354
+// at 16384; 5.07 / 4.04 at 65536), and whole runs take the mixed path's
+// extra launches on every block step (N = 16384, t = 0 -> 1: 6.7 s against
+// 5.2 s in FP64).  The paper-faithful
 // mode keeps the printed scheme: radius 0 (only the self pair and
 // coincident particles take the FP64 path) and no FP64 systems.
 double default_near_factor(int precision)
@@ -223,7 +226,7 @@ double default_near_factor(int precision)
 
 int64_t default_fp64_below(int precision)
 {
-    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 8192 : 0;
+    return (precision == HERMITE_MIXED || precision == HERMITE_MIXED_2F) ? 32768 : 0;
 }
 
 // Blocks of fewer interactions than this are swept in FP64 by the mixed

@@ -763,10 +763,19 @@ __device__ __forceinline__ void finalize(const Sum2F& S, double out[kRows])
 // SEL: the workgroup first selects the block itself (one system of
 // n <= kFusedSelMax; the active list stays in LDS) and computes the plan;
 // workgroup 0 publishes list, n_act, T, plan and counters for the corrector.
+// Occupancy hints (waves per SIMD) where they cost no spill: the cast
+// two-per-lane forms fit four, the split one with FP64 running sums three;
+// the two-float split and fused-selection forms get none.
+template <int PREC, int IPL, bool SPLIT, bool SEL>
+constexpr int sweep_min_waves()
+{
+    return SEL || IPL != 2 ? 1
+           : (!SPLIT && (PREC == 1 || PREC == 3)) ? 4
+           : (SPLIT && PREC == 1) ? 3 : 1;
+}
+
 template <int PREC, bool POT_ONLY, int IPL, bool SPLIT, bool SEL = false, int KR = kMixedK>
-// (The split two-per-lane form with FP64 running sums fits three waves per
-// SIMD without spilling; the two-float and fused-selection forms do not.)
-__global__ void __launch_bounds__(kWG, (SPLIT && IPL == 2 && PREC == 1 && !SEL) ? 3 : 1)
+__global__ void __launch_bounds__(kWG, (sweep_min_waves<PREC, IPL, SPLIT, SEL>()))
 sweep_kernel(SweepArgs a)
 {
     static_assert(!SEL || !POT_ONLY, "the fused selection is for block steps");

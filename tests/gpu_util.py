@@ -57,7 +57,7 @@ def check_mixed(name, got, ref, cond, tol=TOL_MIXED, cond_factor=4.0, max_second
 def fp32_policy(H, ctx, near_factor=3.0):
     """Makes the mixed precisions sweep every system and every block in
     FP32 (with their near field and refinement), as they do by default for
-    N >= 8192 and blocks of at least 5e7 interactions; returns the previous
+    N >= 32768 and blocks of at least 5e7 interactions; returns the previous
     policies for restore_policy."""
     saved = {p: (ctx.get_mixed_policy(p), ctx.get_mixed_small_blocks(p))
              for p in (H.MIXED, H.MIXED_2F)}

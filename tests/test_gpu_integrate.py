@@ -236,16 +236,26 @@ def test_lockstep_block_steps(H, ctx, prec):
 
 
 def test_mixed_small_block_steps_take_fp64(H, ctx):
-    """Block steps with the default mixed policy: while a block's sweep is
+    """Block steps with the default block policy: while a block's sweep is
     below 5e7 interactions it is done in FP64 (with the mixed path's
     flagging reduce and corrector), so the state follows FP64 steps bit for
-    bit; hermite_run and hermite_step agree too."""
+    bit; hermite_run and hermite_step agree too.  (Systems from 8192
+    particles on are swept in FP32 here, so that the block rule decides.)"""
     n = 20000
     x, v, m, _ = _c1_setup(H, n=n, seed=51)
     eps2 = (4.0 / n) ** 2
     params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
     s0 = H.State(x, v, m, TB)
     ctx.initialize(s0, eps2, params, H.FP64)
+    saved = ctx.get_mixed_policy(H.MIXED)
+    ctx.set_mixed_policy(H.MIXED, saved[0], 8192)
+    try:
+        _small_block_steps(H, ctx, s0, eps2, params, n)
+    finally:
+        ctx.set_mixed_policy(H.MIXED, *saved)
+
+
+def _small_block_steps(H, ctx, s0, eps2, params, n):
     sa, sb = s0.clone(), s0.clone()
     checked = 0
     for k in range(16):

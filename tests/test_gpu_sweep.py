@@ -98,7 +98,7 @@ def test_fp64_sweep_parity_variants(H, ctx, variant, n, n_act):
 @pytest.fixture
 def fp32(H, ctx):
     """The mixed precisions sweep every system in FP32 (the default policy
-    does so from N = 8192 on)."""
+    does so from N = 32768 on)."""
     saved = fp32_policy(H, ctx)
     yield
     restore_policy(ctx, saved)
@@ -148,10 +148,10 @@ def test_mixed_near_factor_range(H, ctx, near):
 
 
 def test_mixed_small_systems_take_fp64(H, ctx):
-    """Default policy: a system below fp64_below = 8192 particles is swept
+    """Default policy: a system below fp64_below = 32768 particles is swept
     with the FP64 kernel (same launch shape), so the mixed results equal the
     FP64 ones bit for bit; policy arguments are validated."""
-    assert ctx.get_mixed_policy(H.MIXED) == (3.0, 8192)
+    assert ctx.get_mixed_policy(H.MIXED) == (3.0, 32768)
     assert ctx.get_mixed_policy(H.MIXED_SP) == (0.0, 0)
     n = 4096
     s, *_ = _state(H, n, 12)
@@ -165,22 +165,39 @@ def test_mixed_small_systems_take_fp64(H, ctx):
         with pytest.raises(H.HermiteError) as err:
             ctx.set_mixed_policy(*args)
         assert err.value.code == H.EINVAL
-    assert ctx.get_mixed_policy(H.MIXED) == (3.0, 8192)
+    assert ctx.get_mixed_policy(H.MIXED) == (3.0, 32768)
 
 
 def test_mixed_small_blocks_take_fp64(H, ctx):
-    """Default policy: a mixed sweep of fewer than 5e7 interactions is done
-    by the FP64 kernel (decided on the device from the active count), so it
-    equals the FP64 sweep bit for bit at the same launch shape; a larger one
-    uses FP32 pair arithmetic and meets the mixed bar; the setting is
-    validated."""
-    from oracle import oracle as O
+    """Default block policy: a mixed sweep of fewer than 5e7 interactions is
+    done by the FP64 kernel (decided on the device from the active count),
+    so it equals the FP64 sweep bit for bit at the same launch shape; a
+    larger one uses FP32 pair arithmetic and meets the mixed bar; the
+    setting is validated.  (Systems from 8192 particles on are swept in
+    FP32 here, so that the block rule decides.)"""
     assert ctx.get_mixed_small_blocks(H.MIXED) == 50000000
     assert ctx.get_mixed_small_blocks(H.MIXED_2F) == 50000000
     assert ctx.get_mixed_small_blocks(H.MIXED_SP) == 0
     n = 20000
     s, x, v, m = _state(H, n, 13)
     eps2 = (4.0 / n) ** 2
+    saved = {p: ctx.get_mixed_policy(p) for p in (H.MIXED, H.MIXED_2F)}
+    for p, (near, _) in saved.items():
+        ctx.set_mixed_policy(p, near, 8192)
+    try:
+        _small_blocks_cases(H, ctx, s, x, v, m, eps2, n)
+    finally:
+        for p, args in saved.items():
+            ctx.set_mixed_policy(p, *args)
+    for args in ((H.FP64, 0), (H.MIXED_SP, 10), (H.MIXED, -1)):
+        with pytest.raises(H.HermiteError) as err:
+            ctx.set_mixed_small_blocks(*args)
+        assert err.value.code == H.EINVAL
+    assert ctx.get_mixed_small_blocks(H.MIXED) == 50000000
+
+
+def _small_blocks_cases(H, ctx, s, x, v, m, eps2, n):
+    from oracle import oracle as O
     for n_act, small in ((64, True), (2400, True), (4000, False)):
         idx = _idx(n, n_act, 77)
         ti = torch.from_numpy(idx).cuda()
@@ -195,17 +212,33 @@ def test_mixed_small_blocks_take_fp64(H, ctx):
                 check_mixed("acc", got[0].cpu().numpy()[:, :300], ra, cond[0])
                 check_mixed("jerk", got[1].cpu().numpy()[:, :300], rj, cond[1])
                 check_mixed("pot", got[2].cpu().numpy()[None, :300], rp[None], cond[2])
-    for args in ((H.FP64, 0), (H.MIXED_SP, 10), (H.MIXED, -1)):
+
+
+def test_force_jerk_timed_matches_and_times(H, ctx):
+    """hermite_force_jerk_timed gives hermite_force_jerk's results bit for
+    bit and positive phase times that add up to the whole call; bad
+    arguments are rejected."""
+    n = 9000
+    s, *_ = _state(H, n, 14)
+    eps2 = (4.0 / n) ** 2
+    idx = torch.from_numpy(_idx(n, 3000, 5)).cuda()
+    for prec in (H.FP64, H.MIXED):
+        ref = ctx.force_jerk(s, idx, eps2, prec)
+        a, j, p, ms = ctx.force_jerk_timed(s, idx, eps2, prec, reps=3)
+        torch.cuda.synchronize()
+        assert torch.equal(a, ref[0]) and torch.equal(j, ref[1]) and torch.equal(p, ref[2])
+        assert all(ms[k] > 0 for k in ("plan", "sweep", "finish", "total"))
+        assert abs(ms["plan"] + ms["sweep"] + ms["finish"] - ms["total"]) <= 1e-9 * ms["total"] + 1e-12
+    for kw in ({"reps": 0},):
         with pytest.raises(H.HermiteError) as err:
-            ctx.set_mixed_small_blocks(*args)
+            ctx.force_jerk_timed(s, idx, eps2, H.FP64, **kw)
         assert err.value.code == H.EINVAL
-    assert ctx.get_mixed_small_blocks(H.MIXED) == 50000000
 
 
 def test_mixed_ensemble_straddling_threshold(H, ctx):
-    """An ensemble whose clusters straddle fp64_below runs two kernels:
-    the small clusters' sums equal the FP64 sweep's bit for bit, the large
-    ones meet the mixed bar against the oracle."""
+    """An ensemble whose clusters straddle fp64_below (set to 8192 here)
+    runs two kernels: the small clusters' sums equal the FP64 sweep's bit
+    for bit, the large ones meet the mixed bar against the oracle."""
     from oracle import oracle as O
     from paper_1104_2700_amd import inputs
     sizes = [300, 9000, 1000, 12000, 64]
@@ -220,8 +253,13 @@ def test_mixed_ensemble_straddling_threshold(H, ctx):
     s = H.State(x, v, m)
     s.xp.copy_(s.x); s.vp.copy_(s.v)
     A64, J64, P64 = ctx.force_jerk(s, None, 0.0, H.FP64, clusters=cl)
-    A, J, P = ctx.force_jerk(s, None, 0.0, H.MIXED, clusters=cl)
-    torch.cuda.synchronize()
+    saved = ctx.get_mixed_policy(H.MIXED)
+    ctx.set_mixed_policy(H.MIXED, saved[0], 8192)
+    try:
+        A, J, P = ctx.force_jerk(s, None, 0.0, H.MIXED, clusters=cl)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_mixed_policy(H.MIXED, *saved)
     for c, nc in enumerate(sizes):
         lo, hi = off[c], off[c + 1]
         if nc < 8192:
