@@ -80,6 +80,10 @@ struct SweepArgs {
     // nonzero: the reduce stage flags particles whose estimated mixed
     // error is too large (ref_pos[p] = 1) and plans their FP64 refinement
     int32_t refine;
+    // block-step form of the refinement: a block the plan puts in FP64
+    // (fp64_all) is reduced by the corrector from the sweep's partials, and
+    // the flagging reduce and the refine plan leave it alone
+    int32_t defer_fp64;
     int32_t* ref_pos;          // [n_act_max] a flagged position's slot in the list, or -1
     int32_t* ref_idx;          // [n_act_max] flagged particles (the refine sweep's idx)
     int32_t* ref_p;            // [n_act_max] their active positions
@@ -198,10 +202,12 @@ struct CorrectArgs {
     int32_t* na_seen;          // or null: receives n_act (a run's selection reads the
                                // previous block's size from here, never from a word it
                                // rewrites itself)
+    uint8_t* lv_out;           // [n_act_max] or null: log2 of each position's new step
 };
 
 hipError_t launch_correct(const CorrectArgs& c, hipStream_t st);
-hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& ra, hipStream_t st);
+hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& a, const SweepArgs& ra,
+                                 hipStream_t st);
 
 // Fused block-step stages: selection and the sweep plan in two launches
 // (prediction is folded into the sweep and the corrector), and the
@@ -254,6 +260,9 @@ struct LevelArgs {
     int32_t* na;         // n_act: the previous step's in, this step's out
     int64_t* T;          // block time: the previous step's in, this step's out
     int32_t* idx;        // [n] active list grouped by cluster (C > 1)
+    const uint8_t* lv;   // [n] log2 of the new step of every position of the last block
+                         // (written by the corrector): the re-sort reads these in
+                         // position order instead of gathering dt through perm
     int64_t* counters;
     // ensembles (C > 1): per-cluster step-size orders
     int32_t n_clusters;
@@ -261,6 +270,7 @@ struct LevelArgs {
     int32_t* ccnt;       // [C][64] particles of cluster c with dt = 2^b ticks
     int32_t* ccum;       // [C][64] their running sums over b (steps <= 2^b)
     int32_t* cna;        // [C] size of cluster c's last block
+    int32_t* cst;        // [C] its first position in the last block's list
 };
 
 // Counts the steps of a state and checks that it is one the block scheme

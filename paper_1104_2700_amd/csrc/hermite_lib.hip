@@ -83,7 +83,7 @@ struct hermite_ctx {
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
-    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_na, lvl_bits;
+    Buf lvl_perm, lvl_tmp, lvl_cnt, lvl_cursor, lvl_misc, lvl_na, lvl_bits, lvl_lv, lvl_cst;
     Buf lvl_ccnt, lvl_ccum, lvl_cna;   // ensembles: per-cluster orders
     std::vector<GraphEntry> graphs;
     // grid of the fused select + sweep for the last shape it was sized for
@@ -484,6 +484,7 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_clust
     L.na = (int32_t*)c->step_na.p;
     L.T = (int64_t*)c->step_T.p;
     L.idx = (int32_t*)c->step_idx.p;
+    L.lv = (const uint8_t*)c->lvl_lv.p;
     L.counters = (int64_t*)c->counters.p;
     L.n_clusters = cl ? cl->n_clusters : 1;
     if (cl && cl->n_clusters > 1) {
@@ -491,6 +492,7 @@ LevelArgs level_args(hermite_ctx* c, const hermite_state* s, const hermite_clust
         L.ccnt = (int32_t*)c->lvl_ccnt.p;
         L.ccum = (int32_t*)c->lvl_ccum.p;
         L.cna = (int32_t*)c->lvl_cna.p;
+        L.cst = (int32_t*)c->lvl_cst.p;
     }
     return L;
 }
@@ -510,11 +512,13 @@ int level_init(hermite_ctx* c, const hermite_state* s, const hermite_clusters* c
     CHECK(ensure(c, c->lvl_misc, sizeof(int64_t) * 8));
     CHECK(ensure(c, c->lvl_na, sizeof(int32_t) * 2));
     CHECK(ensure(c, c->lvl_bits, sizeof(uint32_t) * ((s->n + 31) / 32)));
+    CHECK(ensure(c, c->lvl_lv, sizeof(uint8_t) * s->n));
     if (cl && cl->n_clusters > 1) {
         const size_t C = (size_t)cl->n_clusters;
         CHECK(ensure(c, c->lvl_ccnt, sizeof(int32_t) * 64 * C));
         CHECK(ensure(c, c->lvl_ccum, sizeof(int32_t) * 64 * C));
         CHECK(ensure(c, c->lvl_cna, sizeof(int32_t) * C));
+        CHECK(ensure(c, c->lvl_cst, sizeof(int32_t) * C));
     }
     const LevelArgs L = level_args(c, s, cl, p, 0);
     const int64_t init[8] = {0, INT64_MIN, INT64_MAX, 0, 0, 0, 0, 0};
@@ -625,17 +629,21 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     ca.k_max = p->k_max;
     ca.counters = counters;
     ca.predict_i = 1;
-    if (level) ca.na_seen = (int32_t*)c->lvl_na.p;
+    if (level) {
+        ca.na_seen = (int32_t*)c->lvl_na.p;
+        ca.lv_out = (uint8_t*)c->lvl_lv.p;
+    }
     if (a.refine) {
         // mixed sums into the compact outputs with their error flags, the
         // FP64 refine sweep of the flagged particles, then the corrector
         SweepArgs ra;
         CHECK(prepare_refine(c, a, &ra));
+        a.defer_fp64 = 1;
         HIP_OK(launch_reduce_refine(a, ra, tu.variant, grid, st));
         ca.acc1 = out;
         ca.jrk1 = out + 3 * n;
         ca.pot1 = out + 6 * n;
-        HIP_OK(launch_correct_refine(ca, ra, st));
+        HIP_OK(launch_correct_refine(ca, a, ra, st));
     } else {
         HIP_OK(launch_correct_reduce(ca, a, st));
     }
@@ -823,9 +831,8 @@ int hermite_destroy(hermite_ctx* c)
                    &c->rpartial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
                    &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
-                   &c->lvl_cursor, &c->lvl_misc, &c->lvl_na, &c->lvl_ccnt, &c->lvl_ccum,
-                   &c->lvl_cna,
-                   &c->lvl_bits};
+                   &c->lvl_cursor, &c->lvl_misc, &c->lvl_na, &c->lvl_lv, &c->lvl_cst,
+                   &c->lvl_ccnt, &c->lvl_ccum, &c->lvl_cna, &c->lvl_bits};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

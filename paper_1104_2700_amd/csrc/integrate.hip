@@ -468,19 +468,22 @@ constexpr int kLevelOrder = 4096; // one system: blocks listed in particle order
 constexpr int kSelectGrid = 256;  // ensembles: workgroups of the selection
 
 // Particle ids of positions p = p0 + u kWG + tid (u < kLevelBatch) of
-// src[0, cnt) and, with_steps, their step sizes: every load is issued
-// before any is used (addresses clamped to the last position, so none is
-// conditional).
+// src[0, cnt) and, with_steps, their step sizes (log2), from lv[p] when
+// given (the corrector's record, read in position order) else from dt of
+// the id: every load is issued before any is used (addresses clamped to
+// the last position, so none is conditional).
 __device__ __forceinline__ void level_batch(const int32_t* src, const int64_t* dt, int32_t cnt,
                                             int32_t p0, int32_t (&id)[kLevelBatch],
-                                            int (&b)[kLevelBatch], bool with_steps)
+                                            int (&b)[kLevelBatch], bool with_steps,
+                                            const uint8_t* lv = nullptr)
 {
 #pragma unroll
     for (int u = 0; u < kLevelBatch; ++u) {
         const int32_t p = p0 + u * kWG + (int32_t)threadIdx.x;
         id[u] = src[p < cnt ? p : cnt - 1];
+        if (with_steps && lv) b[u] = lv[p < cnt ? p : cnt - 1];
     }
-    if (with_steps) {
+    if (with_steps && !lv) {
         int64_t d[kLevelBatch];
 #pragma unroll
         for (int u = 0; u < kLevelBatch; ++u) d[u] = dt[id[u]];
@@ -522,13 +525,14 @@ struct LevelLds {
 
 // Re-sorts the last block, perm[0, m), by the steps the corrector gave it
 // (a counting sort by step size; staged in LDS up to kLevelLds, else
-// through tmp[0, m)).  Every particle of that block had a step dividing
+// through tmp[0, m)); lv (or null: dt through perm) holds the new steps'
+// log2 by position.  Every particle of that block had a step dividing
 // the block time 2^z * odd and got a new one that divides it, and every
 // particle after it has a larger step, so the whole order stays sorted.
 // S.cnt (the order's step counts) gets the block's counts for steps <= 2^z.
 // All threads of the workgroup call it; it ends with a barrier.
 __device__ void level_resort(const LevelArgs& L, int32_t* perm, int32_t* tmp, int32_t m, int z,
-                             LevelLds& S)
+                             LevelLds& S, const uint8_t* lv)
 {
     const int tid = threadIdx.x;
     constexpr int kStride = kWG * kLevelBatch;
@@ -538,7 +542,7 @@ __device__ void level_resort(const LevelArgs& L, int32_t* perm, int32_t* tmp, in
     for (int32_t p0 = 0; p0 < m; p0 += kStride) {
         int32_t id[kLevelBatch];
         int b[kLevelBatch];
-        level_batch(perm, L.dt, m, p0, id, b, true);
+        level_batch(perm, L.dt, m, p0, id, b, true, lv);
 #pragma unroll
         for (int u = 0; u < kLevelBatch; ++u) {
             const int32_t p = p0 + u * kWG + tid;
@@ -567,7 +571,7 @@ __device__ void level_resort(const LevelArgs& L, int32_t* perm, int32_t* tmp, in
         for (int32_t p0 = 0; p0 < m; p0 += kStride) {
             int32_t id[kLevelBatch];
             int b[kLevelBatch];
-            level_batch(perm, L.dt, m, p0, id, b, true);
+            level_batch(perm, L.dt, m, p0, id, b, true, lv);
 #pragma unroll
             for (int u = 0; u < kLevelBatch; ++u)
                 if (p0 + u * kWG + tid < m)
@@ -626,7 +630,8 @@ __global__ void __launch_bounds__(kWG) level_select_kernel(LevelArgs L, SweepArg
     if (tid < 64) S.cnt[tid] = L.cnt[tid];
     if (na_prev > 0) {
         Tlast = *L.T;
-        level_resort(L, L.perm, L.tmp, na_prev, __builtin_ctzll((unsigned long long)Tlast), S);
+        level_resort(L, L.perm, L.tmp, na_prev, __builtin_ctzll((unsigned long long)Tlast), S,
+                     L.lv);
         if (tid < 64) L.cnt[tid] = S.cnt[tid];
         if (tid == 0) L.misc[0] = Tlast;
     } else {
@@ -704,7 +709,10 @@ __global__ void __launch_bounds__(kWG) cl_build_kernel(LevelArgs L)
         base[tid] = x - k;
         L.ccnt[c * 64 + tid] = k;
         L.ccum[c * 64 + tid] = x;
-        if (tid == 0) L.cna[c] = 0;
+        if (tid == 0) {
+            L.cna[c] = 0;
+            L.cst[c] = 0;
+        }
     }
     __syncthreads();
     for (int64_t i = o0 + tid; i < o1; i += kWG) {
@@ -729,18 +737,20 @@ __global__ void __launch_bounds__(kWG) cl_resort_kernel(LevelArgs L)
     const int32_t na_prev = *L.na_prev;
     const int64_t T_prev = *L.T;
     const int32_t m = L.cna[c];
+    const int32_t pst = L.cst[c];
     const int64_t o = L.offsets[c], o1 = L.offsets[c + 1];
     const int32_t old = tid < 64 ? L.ccnt[c * 64 + tid] : 0;
     if (na_prev <= 0) return;
     if (c == 0 && tid == 0) L.misc[0] = T_prev;
     if (m <= 0) return;
-    if ((int64_t)m > o1 - o) {
+    if ((int64_t)m > o1 - o || pst < 0 || (int64_t)pst + m > L.n) {
         if (tid == 0)
             __hip_atomic_store(&L.misc[4], (int64_t)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
     if (tid < 64) S.cnt[tid] = old;
-    level_resort(L, L.perm + o, L.tmp + o, m, __builtin_ctzll((unsigned long long)T_prev), S);
+    level_resort(L, L.perm + o, L.tmp + o, m, __builtin_ctzll((unsigned long long)T_prev), S,
+                 L.lv ? L.lv + pst : nullptr);
     if (tid < 64) {
         const int32_t k = S.cnt[tid];
         L.ccnt[c * 64 + tid] = k;
@@ -753,19 +763,30 @@ __global__ void __launch_bounds__(kWG) cl_resort_kernel(LevelArgs L)
 // Every workgroup derives the block time and every cluster's count from
 // the same tables (nothing here writes them), lists the blocks of clusters
 // g, g + G, ... and records their sizes for the next re-sort; workgroup 0
-// publishes the block time, n_act, the clusters' first positions and the
-// sweep plan.
+// publishes the block time, n_act and the sweep plan (from the starts and
+// ranges it holds in LDS, so the plan waits on no global load).
 __global__ void __launch_bounds__(kWG) cl_select_kernel(LevelArgs L, SweepArgs sa)
 {
     __shared__ int32_t s_start[kLdsClusters + 1];
+    __shared__ int64_t s_off[kLdsClusters + 1];
     __shared__ int32_t s_scan[kWG / 64];
     __shared__ int32_t s_bm;
     const int tid = threadIdx.x, G = gridDim.x, g = blockIdx.x;
     const int C = L.n_clusters;
+    // the loads that do not depend on each other, issued together: the
+    // first kWG entries of this workgroup's first cluster's order among
+    // them (most blocks take fewer)
     const int64_t Tlast = L.misc[0];
+    const int32_t cnt_b = tid < 64 ? L.cnt[tid] : 0;
+    int32_t pre = 0;
+    if (g < C) {
+        const int64_t o = L.offsets[g];
+        if (o + tid < L.offsets[g + 1]) pre = L.perm[o + tid];
+    }
+    for (int c = tid; c <= C; c += kWG) s_off[c] = L.offsets[c];
     // the smallest occupied step of the ensemble (one lane per step size)
     if (tid < 64) {
-        const unsigned long long occ = __ballot(L.cnt[tid] > 0);
+        const unsigned long long occ = __ballot(cnt_b > 0);
         if (tid == 0) s_bm = occ ? __builtin_ctzll(occ) : 64;
     }
     __syncthreads();
@@ -797,22 +818,23 @@ __global__ void __launch_bounds__(kWG) cl_select_kernel(LevelArgs L, SweepArgs s
     __syncthreads();
     for (int c = g; c < C; c += G) {
         const int32_t st = s_start[c], cnt = s_start[c + 1] - st;
-        const int32_t* src = L.perm + L.offsets[c];
+        const int32_t* src = L.perm + s_off[c];
         for (int32_t k = tid; k < cnt; k += kWG) {
-            L.idx[st + k] = src[k];
+            L.idx[st + k] = (c == g && k < kWG) ? pre : src[k];
             sa.act_cluster[st + k] = c;
         }
-        if (tid == 0) L.cna[c] = cnt;
+        if (tid == 0) {
+            L.cna[c] = cnt;
+            L.cst[c] = st;
+        }
     }
     if (g != 0) return;
-    for (int c = tid; c < C; c += kWG) sa.act_start[c] = s_start[c];
     if (tid == 0) {
         *L.T = Tn;
         *L.na = na;
         count_step(L.counters, Tn, na);
     }
-    __syncthreads();   // act_start complete before the plan reads it
-    plan_body(sa, na);
+    plan_body(sa, na, s_start, s_off);
 }
 
 // ---- predictor (equations (xpred), (vpred)) -----------------------------
@@ -911,7 +933,9 @@ __device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double
     if (c.crit_out) c.crit_out[p] = crit;
     const int k_old = c.tick_bits - log2_step(dt_old);
     int cl;
-    c.dt[i] = quantize_dt(crit, k_old, T, c.tick_bits, c.k_min, c.k_max, &cl);
+    const int64_t dt_new = quantize_dt(crit, k_old, T, c.tick_bits, c.k_min, c.k_max, &cl);
+    c.dt[i] = dt_new;
+    if (c.lv_out) c.lv_out[p] = (uint8_t)log2_step(dt_new);
     if (cl && c.counters) atomicAdd((unsigned long long*)&c.counters[2], 1ull);
 }
 
@@ -934,9 +958,8 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
 // The block-step corrector: sums the sweep's j-chunk partials of position p
 // in fixed order (the reduce stage) and corrects in the same kernel.
 // Grid-stride: a thread per particle for few chunks, a wave for many.
-__global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, SweepArgs sa)
+__device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, int na)
 {
-    const int na = sa.plan->n_act;
     if (c.na_seen && blockIdx.x == 0 && threadIdx.x == 0) *c.na_seen = na;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     if (thread_reduce(sa.plan->s_max, na)) {
@@ -962,11 +985,23 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
     }
 }
 
+__global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, SweepArgs sa)
+{
+    correct_reduce_body(c, sa, sa.plan->n_act);
+}
+
 // The block-step corrector of a refined mixed sweep: the mixed sums from
 // the compact outputs, or, for a flagged position, the FP64 refine
-// sweep's partials summed in chunk order.
-__global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, SweepArgs ra)
+// sweep's partials summed in chunk order.  A block the plan put in FP64
+// (fp64_all: the flagging reduce and the refine plan left it alone) is
+// reduced from the sweep's own partials, as correct_reduce_kernel does.
+__global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, SweepArgs a,
+                                                             SweepArgs ra)
 {
+    if (a.plan->fp64_all) {
+        correct_reduce_body(c, a, a.plan->n_act);
+        return;
+    }
     const int na = *c.n_act_dev;
     if (c.na_seen && blockIdx.x == 0 && threadIdx.x == 0) *c.na_seen = na;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
@@ -1167,10 +1202,11 @@ hipError_t launch_correct_reduce(const CorrectArgs& c, const SweepArgs& sa, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& ra, hipStream_t st)
+hipError_t launch_correct_refine(const CorrectArgs& c, const SweepArgs& a, const SweepArgs& ra,
+                                 hipStream_t st)
 {
     hipLaunchKernelGGL(correct_refine_kernel, dim3(reduce_grid(c.n_act_max)), dim3(kWG), 0, st,
-                       c, ra);
+                       c, a, ra);
     return hipGetLastError();
 }
 

@@ -127,6 +127,29 @@ __device__ inline int32_t select_in_lds(const int64_t* t, const int64_t* dt, int
 // list of (cluster, i-tile, j-chunk) items, and adds the sweep's
 // interaction count to the counters.
 // ------------------------------------------------------------------------
+// Quotients of non-negative integers (b > 0).  The operands fit 32 bits in
+// every plan of a realistic size, and the 32-bit division is a short
+// sequence on the GPU, where a 64-bit one is a long software routine (a
+// dozen of them made up most of a plan's latency).
+__host__ __device__ inline int64_t div_floor(int64_t a, int64_t b)
+{
+    if ((((uint64_t)a | (uint64_t)b) >> 32) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+
+__host__ __device__ inline int64_t div_ceil(int64_t a, int64_t b)
+{
+    const int64_t q = div_floor(a, b);
+    return q * b != a ? q + 1 : q;
+}
+
+// ceil(a / b) for b a power of two (a shift), else div_ceil.
+__host__ __device__ inline int64_t div_ceil_p2(int64_t a, int64_t b)
+{
+    if ((b & (b - 1)) == 0) return (a + b - 1) >> __builtin_ctzll((unsigned long long)b);
+    return div_ceil(a, b);
+}
+
 // The split for na active particles of (at most) c_act active clusters:
 // lanes per particle L, particles per item ti, chunk length jc.  (Also
 // evaluated on the host, to size the grid of the fused select + sweep.)
@@ -140,26 +163,26 @@ __host__ __device__ inline void plan_split(const SweepArgs& a, int32_t na, int64
     const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
     int64_t s_cap = a.one_chunk ? 1 : (a.n_cmax + kTJ - 1) / kTJ;
     if (na > 0) {
-        const int64_t buf_cap = a.partial_cap / (kRows * (int64_t)na);
+        const int64_t buf_cap = div_floor(a.partial_cap, kRows * (int64_t)na);
         if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
     }
     // Fewest lanes per particle that (a) still yields enough items and
     // (b) keeps tiles at least half full given the active particles per
     // active cluster: more particles per item means more work per staged j
     // tile, but a tile larger than a cluster's active run leaves lanes idle.
-    const int64_t per_cluster = (na + c_act - 1) / c_act;
+    const int64_t per_cluster = div_ceil(na, c_act);
     int32_t L = 1;
     for (; L < 64; L <<= 1) {
         const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-        const int64_t tiles = (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0);
+        const int64_t tiles = div_ceil_p2(na, ti_l) + (C > 1 ? c_act : 0);
         if (tiles * s_cap >= want && ti_l <= 2 * per_cluster) break;
     }
     const int64_t ti_l = (int64_t)a.ipl * (kWG / L);
-    const int64_t tiles = na > 0 ? (na + ti_l - 1) / ti_l + (C > 1 ? c_act : 0) : 1;
-    int64_t S = (want + tiles - 1) / tiles;
+    const int64_t tiles = na > 0 ? div_ceil_p2(na, ti_l) + (C > 1 ? c_act : 0) : 1;
+    int64_t S = div_ceil(want, tiles);
     if (S > s_cap) S = s_cap;
     if (S < 1) S = 1;
-    int64_t jc = (a.n_cmax + S - 1) / S;
+    int64_t jc = div_ceil(a.n_cmax, S);
     const int64_t jmin = (int64_t)L * a.min_j_per_lane;
     if (jc < jmin) jc = jmin;
     jc = (jc + kTJ - 1) / kTJ * kTJ;
@@ -191,38 +214,57 @@ __device__ inline int32_t block_exscan(int32_t v, int32_t* total)
     return off;
 }
 
-// Block-wide (kWG threads) sum of an int64 and maximum of an int32, by
-// wave shuffles and one round through LDS; every thread calls it and gets
-// both results.
-__device__ inline void block_sum_max(int64_t* sum, int32_t* mx)
+// One LDS round for three block-wide results (all kWG threads call it):
+// the exclusive scan of v (returned; *total gets the sum), the sum of
+// *sum and the maximum of *mx (both replaced by the block's).
+__device__ inline int32_t block_exscan_sum_max(int32_t v, int32_t* total, int64_t* sum,
+                                               int32_t* mx)
 {
+    __shared__ int32_t s_w[kWG / 64];
     __shared__ int64_t s_s[kWG / 64];
     __shared__ int32_t s_m[kWG / 64];
-    int64_t v = *sum;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(x, o);
+        if (lane >= o) x += u;
+    }
+    int64_t sv = *sum;
     int32_t m = *mx;
     for (int o = 32; o > 0; o >>= 1) {
-        v += __shfl_xor(v, o);
+        sv += __shfl_xor(sv, o);
         const int32_t u = __shfl_xor(m, o);
         m = u > m ? u : m;
     }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_s[wave] = v;
+    if (lane == 63) {
+        s_w[wave] = x;
+        s_s[wave] = sv;
         s_m[wave] = m;
     }
     __syncthreads();
-    v = 0;
+    int32_t off = x - v, tot = 0;
+    sv = 0;
     m = s_m[0];
     for (int w = 0; w < kWG / 64; ++w) {
-        v += s_s[w];
+        off += w < wave ? s_w[w] : 0;
+        tot += s_w[w];
+        sv += s_s[w];
         m = s_m[w] > m ? s_m[w] : m;
     }
     __syncthreads();
-    *sum = v;
+    *total = tot;
+    *sum = sv;
     *mx = m;
+    return off;
 }
 
-__device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
+// s_start / s_off (optional, LDS): every cluster's first active position
+// (s_start[C] = na) and its particle range, as the ensemble selection has
+// them at hand; without them the plan reads offsets and the selection's
+// act_start from global memory, or searches idx.
+__device__ inline void plan_body(const SweepArgs& a, int32_t na_in,
+                                 const int32_t* s_start = nullptr, const int64_t* s_off = nullptr)
 {
     const int tid = threadIdx.x;
     const int32_t na = na_in < 0 ? 0 : (na_in > a.n_act_max ? a.n_act_max : na_in);
@@ -233,8 +275,8 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
             int32_t L, ti;
             int64_t jc;
             plan_split(a, na, 1, &L, &ti, &jc);
-            const int32_t tiles = (na + ti - 1) / ti;
-            const int32_t ch = na > 0 ? (int32_t)((a.n + jc - 1) / jc) : 0;
+            const int32_t tiles = (int32_t)div_ceil_p2(na, ti);
+            const int32_t ch = na > 0 ? (int32_t)div_ceil(a.n, jc) : 0;
             a.act_start[0] = 0;
             a.act_cnt[0] = na;
             a.chunks[0] = ch;
@@ -261,11 +303,12 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
     // 1. the active run of every cluster (idx is ascending)
     int32_t nact_c = 0;
     for (int c = c0; c < c1; ++c) {
-        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
-        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
+        const int64_t o0 = s_off ? s_off[c] : a.offsets[c];
+        const int64_t o1 = s_off ? s_off[c + 1] : a.offsets[c + 1];
         int32_t st, cnt;
-        if (C == 1) {
-            st = 0; cnt = na;
+        if (s_start) {
+            st = s_start[c];
+            cnt = s_start[c + 1] - st;
         } else if (a.sel_clusters) {
             // starts recorded by the selection (only when it had active
             // particles); a cluster starting at n (empty, at the end) has
@@ -303,26 +346,30 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in)
     int64_t jc;
     plan_split(a, na, c_act > 0 ? c_act : 1, &L, &ti, &jc);
 
-    // 3. work items per cluster and their offsets
+    // 3. work items per cluster and their offsets (a thread's clusters'
+    // item counts kept in registers when it owns at most kPlanPer of them)
+    constexpr int kPlanPer = kLdsClusters / kWG;
+    int32_t items_c[kPlanPer];
     int32_t local = 0, cmax = 0;
     int64_t inter = 0;
     for (int c = c0; c < c1; ++c) {
-        const int64_t o0 = (C == 1) ? 0 : a.offsets[c];
-        const int64_t o1 = (C == 1) ? a.n : a.offsets[c + 1];
-        const int32_t cnt = a.act_cnt[c];
-        const int32_t tiles = (cnt + ti - 1) / ti;
-        const int32_t ch = cnt > 0 ? (int32_t)((o1 - o0 + jc - 1) / jc) : 0;
+        const int64_t o0 = s_off ? s_off[c] : a.offsets[c];
+        const int64_t o1 = s_off ? s_off[c + 1] : a.offsets[c + 1];
+        const int32_t cnt = s_start ? s_start[c + 1] - s_start[c] : a.act_cnt[c];
+        const int32_t tiles = (int32_t)div_ceil_p2(cnt, ti);
+        const int32_t ch = cnt > 0 ? (int32_t)div_ceil(o1 - o0, jc) : 0;
         a.chunks[c] = ch;
+        if (c - c0 < kPlanPer) items_c[c - c0] = tiles * ch;
         local += tiles * ch;
         cmax = ch > cmax ? ch : cmax;
         inter += (int64_t)cnt * (o1 - o0);
     }
     int32_t total;
-    int32_t base = block_exscan(local, &total);
-    block_sum_max(&inter, &cmax);
+    int32_t base = block_exscan_sum_max(local, &total, &inter, &cmax);
     for (int c = c0; c < c1; ++c) {
         a.item_off[c] = base;
-        base += ((a.act_cnt[c] + ti - 1) / ti) * a.chunks[c];
+        base += c - c0 < kPlanPer ? items_c[c - c0]
+                                  : (int32_t)div_ceil_p2(a.act_cnt[c], ti) * a.chunks[c];
     }
     if (tid == 0) {
         a.item_off[C] = total;

@@ -815,8 +815,8 @@ sweep_kernel(SweepArgs a)
         plan_split(a, na, 1, &L_, &ti_, &jc);
         L = L_;
         ti = ti_;
-        s_max = na > 0 ? (int)((a.n + jc - 1) / jc) : 0;
-        total = ((na + ti - 1) / ti) * s_max;
+        s_max = na > 0 ? (int)div_ceil(a.n, jc) : 0;
+        total = (int)div_ceil_p2(na, ti) * s_max;
         idx_lds = s_idx;
         if (blockIdx.x == 0) {
             for (int p = tid; p < na; p += kWG) a.sel_idx_out[p] = s_idx[p];
@@ -1110,6 +1110,7 @@ __global__ void __launch_bounds__(kWG) reduce_kernel(SweepArgs a)
 // trip counts over the workgroup (the compaction synchronises it).
 __global__ void __launch_bounds__(kWG) reduce_flag_kernel(SweepArgs a)
 {
+    if (a.defer_fp64 && a.plan->fp64_all) return;
     const int na = a.plan->n_act;
     if (thread_reduce(a.plan->s_max, na)) {
         for (int u = blockIdx.x; u * kWG < na; u += gridDim.x) {
@@ -1145,6 +1146,10 @@ __global__ void __launch_bounds__(kWG) reduce_flag_kernel(SweepArgs a)
 // One workgroup: the refine list and the plan of the refine sweep ra.
 __global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs ra)
 {
+    if (a.defer_fp64 && a.plan->fp64_all) {
+        plan_body(ra, 0);   // nothing to refine: the refine sweep leaves at once
+        return;
+    }
     const int na = a.plan->n_act;
     const int unit = thread_reduce(a.plan->s_max, na) ? kWG : kWG / 64;
     const int32_t cnt = build_refine_list(a, ra, na, unit);

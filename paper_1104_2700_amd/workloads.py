@@ -551,7 +551,7 @@ def main(argv=None):
                     help="c3, c4, c5: run in this precision instead of the configured one")
     ap.add_argument("--fp64-below", type=int, default=None,
                     help="mixed precisions: sweep systems below this size in FP64 "
-                         "(library default 8192; 0: every system in FP32)")
+                         "(library default 32768; 0: every system in FP32)")
     ap.add_argument("--etas", default=None,
                     help="e3: comma-separated eta values (default 0.0025 .. 0.08)")
     ap.add_argument("--small-blocks", type=int, default=None,
