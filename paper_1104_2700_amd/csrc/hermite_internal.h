@@ -81,8 +81,9 @@ struct SweepArgs {
     // error is too large (ref_pos[p] = 1) and plans their FP64 refinement
     int32_t refine;
     // block-step form of the refinement: a block the plan puts in FP64
-    // (fp64_all) is reduced by the corrector from the sweep's partials, and
-    // the flagging reduce and the refine plan leave it alone
+    // (fp64_all) is swept by the refine sweep's launch, with the whole block
+    // as its list, and reduced by the corrector; no other sweep launch and
+    // not the flagging reduce touch it
     int32_t defer_fp64;
     int32_t* ref_pos;          // [n_act_max] a flagged position's slot in the list, or -1
     int32_t* ref_idx;          // [n_act_max] flagged particles (the refine sweep's idx)

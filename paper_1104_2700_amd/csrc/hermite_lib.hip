@@ -344,6 +344,7 @@ void fill_refine(const SweepScratch& sc, const SweepArgs& a, SweepArgs* ra)
     ra->partial = sc.rpartial;
     ra->partial_cap = sc.rpartial_cap;
     ra->refine = 0;
+    ra->defer_fp64 = 0;
     ra->near_factor = 0.0;
     ra->fp64_below = 0;
     ra->fp64_inter_below = 0;
@@ -564,6 +565,9 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
     CHECK(prepare_sweep(c, s, cl, s->xp, s->vp, aidx, na, (int32_t)n, eps2, precision, tu, out,
                         out + 3 * n, out + 6 * n, &a));
     a.ipl = (tu.variant & 1) ? 2 : 1;
+    // a block the plan puts in FP64 takes the refine sweep's launch (over
+    // the whole block) and the corrector's reduce
+    a.defer_fp64 = a.refine;
     // with clusters the selection records the active runs and clusters
     a.act_cluster = cl ? (int32_t*)c->step_acl.p : nullptr;
     a.sel_clusters = cl ? 1 : 0;
@@ -638,7 +642,6 @@ int enqueue_step(hermite_ctx* c, const hermite_state* s, const hermite_clusters*
         // FP64 refine sweep of the flagged particles, then the corrector
         SweepArgs ra;
         CHECK(prepare_refine(c, a, &ra));
-        a.defer_fp64 = 1;
         HIP_OK(launch_reduce_refine(a, ra, tu.variant, grid, st));
         ca.acc1 = out;
         ca.jrk1 = out + 3 * n;

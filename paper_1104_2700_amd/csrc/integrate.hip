@@ -993,13 +993,13 @@ __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, Swee
 // The block-step corrector of a refined mixed sweep: the mixed sums from
 // the compact outputs, or, for a flagged position, the FP64 refine
 // sweep's partials summed in chunk order.  A block the plan put in FP64
-// (fp64_all: the flagging reduce and the refine plan left it alone) is
-// reduced from the sweep's own partials, as correct_reduce_kernel does.
+// (fp64_all: the refine sweep swept all of it, in list order) is reduced
+// from the refine sweep's partials, as correct_reduce_kernel does.
 __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, SweepArgs a,
                                                              SweepArgs ra)
 {
     if (a.plan->fp64_all) {
-        correct_reduce_body(c, a, a.plan->n_act);
+        correct_reduce_body(c, ra, ra.plan->n_act);
         return;
     }
     const int na = *c.n_act_dev;

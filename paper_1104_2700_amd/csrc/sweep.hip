@@ -856,6 +856,7 @@ sweep_kernel(SweepArgs a)
         const bool none64 = fp64_all == 0 && (a.n_clusters == 1 ? a.n >= a.fp64_below
                                                                  : a.fp64_below <= 1);
         if ((a.kind == 1 && all64) || (a.kind == 2 && none64)) return;
+        if (a.kind == 2 && a.defer_fp64 && fp64_all != 0) return;   // the refine launch's
     }
     const int rows = kWG / L;          // lanes' slots per particle row
     const int slot = tid / L;
@@ -1147,7 +1148,14 @@ __global__ void __launch_bounds__(kWG) reduce_flag_kernel(SweepArgs a)
 __global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs ra)
 {
     if (a.defer_fp64 && a.plan->fp64_all) {
-        plan_body(ra, 0);   // nothing to refine: the refine sweep leaves at once
+        // an FP64 block: the refine sweep takes all of it, in list order
+        // (its clusters' runs where the sweep's are)
+        const int na = a.plan->n_act;
+        for (int k = threadIdx.x; k < na; k += kWG) a.ref_idx[k] = a.idx ? a.idx[k] : k;
+        if (a.n_clusters > 1)
+            for (int c = threadIdx.x; c < a.n_clusters; c += kWG) ra.act_start[c] = a.act_start[c];
+        __syncthreads();   // act_start complete before the plan reads it
+        plan_body(ra, na);
         return;
     }
     const int na = a.plan->n_act;
@@ -1257,9 +1265,11 @@ void launch_sweep_kernels(SweepArgs a, int precision, int variant, int grid, boo
     } else if (a.n_cmax < a.fp64_below) {
         go(0, 0);                          // every system is small
     } else if (straddle || (!sel && a.fp64_inter_below > 0)) {
-        // the plan decides on the device, per block, which items are FP64
+        // the plan decides on the device, per block, which items are FP64;
+        // in a block step the refine sweep's launch takes an FP64 block, so
+        // only small systems need an FP64 launch here
         go(precision, 1);
-        go(0, 2);
+        if (straddle || !a.defer_fp64) go(0, 2);
     } else {
         go(precision, 0);                  // no item is
     }
