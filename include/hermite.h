@@ -208,7 +208,7 @@ int hermite_force_jerk_timed(hermite_ctx* ctx, const hermite_state* s,
  * fresh context's launch shape and mixed-precision policy, except that the
  * device counters are not updated.  Its scratch (plan, cluster tables,
  * partial sums, refinement lists) is one static device array of
- * HERMITE_NOALLOC_SCRATCH_BYTES (about 43 MB) that each GPU the library
+ * HERMITE_NOALLOC_SCRATCH_BYTES (about 35 MB) that each GPU the library
  * runs on holds until the process ends; it limits a call to
  * HERMITE_NOALLOC_MAX_ACTIVE active particles and
  * HERMITE_NOALLOC_MAX_CLUSTERS clusters (EINVAL beyond).  The array's
@@ -219,7 +219,7 @@ int hermite_force_jerk_timed(hermite_ctx* ctx, const hermite_state* s,
  * calls. */
 #define HERMITE_NOALLOC_MAX_ACTIVE   65536
 #define HERMITE_NOALLOC_MAX_CLUSTERS 1024
-#define HERMITE_NOALLOC_SCRATCH_BYTES 43094540
+#define HERMITE_NOALLOC_SCRATCH_BYTES 34705932
 int hermite_force_jerk_noalloc(const hermite_state* s, const hermite_clusters* cl,
                                const int32_t* idx, const int32_t* n_act_dev,
                                int32_t n_act_max, double eps2, int precision,

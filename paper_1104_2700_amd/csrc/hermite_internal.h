@@ -80,10 +80,10 @@ struct SweepArgs {
     // nonzero: the reduce stage flags particles whose estimated mixed
     // error is too large (ref_pos[p] = 1) and plans their FP64 refinement
     int32_t refine;
-    // block-step form of the refinement: a block the plan puts in FP64
-    // (fp64_all) is swept by the refine sweep's launch, with the whole block
-    // as its list, and reduced by the corrector; no other sweep launch and
-    // not the flagging reduce touch it
+    // with refinement: a block the plan puts in FP64 (fp64_all) is swept by
+    // the refine sweep's launch, with the whole block as its list, and its
+    // sums taken from there by the corrector (block steps) or the scatter
+    // (force calls); no other sweep launch and not the flagging reduce touch it
     int32_t defer_fp64;
     int32_t* ref_pos;          // [n_act_max] a flagged position's slot in the list, or -1
     int32_t* ref_idx;          // [n_act_max] flagged particles (the refine sweep's idx)

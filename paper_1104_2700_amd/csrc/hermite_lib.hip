@@ -79,7 +79,7 @@ struct hermite_ctx {
     // refinement of mixed sweeps: flags and lists, the refine sweep's plan,
     // per-cluster tables and partial sums, and the flagging reduce's ticket
     Buf ref_pos, ref_idx, ref_p, ref_tmp, ref_ucnt, ref_ccnt, rplan, ract_start, ract_cnt,
-        rchunks, ritem_off, rpartial;
+        rchunks, ritem_off;
     Buf sel_min, sel_cnt;
     Buf step_idx, step_na, step_T, step_out, step_acl, phi, counters, ticket, flag;
     // step-size order of a run (hermite_run)
@@ -250,20 +250,15 @@ struct SweepScratch {
     int32_t *ref_ucnt, *ref_ccnt;                       // [n_act_max / 4 + 1], [C]
     SweepPlan* rplan;
     int32_t *ract_start, *ract_cnt, *rchunks, *ritem_off;
-    double* rpartial;
-    int64_t rpartial_cap;
 };
 
-// Partial-sum capacity of a sweep and of its refine sweep (doubles) for an
-// active count: room for 32 and 4 j-chunks of every active particle.
+// Partial-sum capacity of a sweep (doubles) for an active count: room for
+// 32 j-chunks of every active particle.  The refine sweep reuses the same
+// buffer: its partials are written after the flagging reduce has read the
+// sweep's.
 int64_t partial_cap_for(int32_t n_act_max)
 {
     return (int64_t)kRows * 32 * std::max<int64_t>(n_act_max, 4096);
-}
-
-int64_t rpartial_cap_for(int32_t n_act_max)
-{
-    return (int64_t)kRows * 4 * std::max<int64_t>(n_act_max, 4096);
 }
 
 // True when a sweep of this precision and these systems runs the FP64
@@ -341,8 +336,11 @@ void fill_refine(const SweepScratch& sc, const SweepArgs& a, SweepArgs* ra)
     ra->act_cluster = nullptr;
     // with clusters the refine list's builder writes each cluster's run start
     ra->sel_clusters = a.n_clusters > 1 ? 1 : 0;
-    ra->partial = sc.rpartial;
-    ra->partial_cap = sc.rpartial_cap;
+    // the sweep's partial sums are consumed (by the flagging reduce) before
+    // the refine sweep writes its own, so both use one buffer; an FP64 block
+    // then gets the sweep's own split
+    ra->partial = sc.partial;
+    ra->partial_cap = sc.partial_cap;
     ra->refine = 0;
     ra->defer_fp64 = 0;
     ra->near_factor = 0.0;
@@ -388,7 +386,6 @@ int ctx_scratch(hermite_ctx* c, int C, int32_t n_act_max, bool refine, SweepScra
         CHECK(ensure(c, c->ract_cnt, sizeof(int32_t) * C));
         CHECK(ensure(c, c->rchunks, sizeof(int32_t) * C));
         CHECK(ensure(c, c->ritem_off, sizeof(int32_t) * (C + 1)));
-        CHECK(ensure(c, c->rpartial, sizeof(double) * rpartial_cap_for(n_act_max)));
         sc->ref_pos = (int32_t*)c->ref_pos.p;
         sc->ref_idx = (int32_t*)c->ref_idx.p;
         sc->ref_p = (int32_t*)c->ref_p.p;
@@ -400,8 +397,6 @@ int ctx_scratch(hermite_ctx* c, int C, int32_t n_act_max, bool refine, SweepScra
         sc->ract_cnt = (int32_t*)c->ract_cnt.p;
         sc->rchunks = (int32_t*)c->rchunks.p;
         sc->ritem_off = (int32_t*)c->ritem_off.p;
-        sc->rpartial = (double*)c->rpartial.p;
-        sc->rpartial_cap = (int64_t)(c->rpartial.bytes / sizeof(double));
     }
     return HERMITE_OK;
 }
@@ -680,18 +675,17 @@ std::string step_key(const hermite_state* s, const hermite_clusters* cl, double 
 // Scratch of hermite_force_jerk_noalloc: one file-scope device array, laid
 // out as the context scratch of a sweep of at most kNoAllocMaxActive active
 // particles in at most kNoAllocMaxClusters systems (partial sums for 8
-// j-chunks of every active particle, 2 for the refine sweep).  Each device
+// j-chunks of every active particle, shared with the refine sweep).  Each device
 // holds its own copy, at the address hipGetSymbolAddress gives on it.
 // ---------------------------------------------------------------------------
 constexpr int64_t kNoAllocMaxActive = HERMITE_NOALLOC_MAX_ACTIVE;
 constexpr int kNoAllocMaxClusters = HERMITE_NOALLOC_MAX_CLUSTERS;
 constexpr int64_t kNoAllocPartial = (int64_t)kRows * 8 * kNoAllocMaxActive;    // doubles
-constexpr int64_t kNoAllocRPartial = (int64_t)kRows * 2 * kNoAllocMaxActive;   // doubles
 constexpr int64_t kNoAllocInts =
     2 * (3 * (int64_t)kNoAllocMaxClusters + (kNoAllocMaxClusters + 1)) +  // tables
     4 * kNoAllocMaxActive + (kNoAllocMaxActive / (kWG / 64) + 1) +         // refine lists
     kNoAllocMaxClusters;                                                    // per-cluster counts
-constexpr size_t kNoAllocBytes = sizeof(double) * (kNoAllocPartial + kNoAllocRPartial) +
+constexpr size_t kNoAllocBytes = sizeof(double) * kNoAllocPartial +
                                  2 * 256 +                                  // the two plans
                                  sizeof(int32_t) * kNoAllocInts;
 static_assert(sizeof(SweepPlan) <= 256, "plan slot");
@@ -739,9 +733,7 @@ SweepScratch noalloc_carve(unsigned char* base)
     double* d = (double*)base;
     sc.partial = d;
     sc.partial_cap = kNoAllocPartial;
-    sc.rpartial = d + kNoAllocPartial;
-    sc.rpartial_cap = kNoAllocRPartial;
-    unsigned char* q = (unsigned char*)(d + kNoAllocPartial + kNoAllocRPartial);
+    unsigned char* q = (unsigned char*)(d + kNoAllocPartial);
     sc.plan = (SweepPlan*)q;
     sc.rplan = (SweepPlan*)(q + 256);
     int32_t* i = (int32_t*)(q + 512);
@@ -831,7 +823,7 @@ int hermite_destroy(hermite_ctx* c)
                    &c->partial, &c->ref_pos, &c->ref_idx, &c->ref_p, &c->ref_tmp,
                    &c->ref_ucnt, &c->ref_ccnt,
                    &c->rplan, &c->ract_start, &c->ract_cnt, &c->rchunks, &c->ritem_off,
-                   &c->rpartial, &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
+                   &c->sel_min, &c->sel_cnt, &c->step_idx, &c->step_na,
                    &c->step_T, &c->step_out, &c->step_acl, &c->phi, &c->counters,
                    &c->ticket, &c->flag, &c->lvl_perm, &c->lvl_tmp, &c->lvl_cnt,
                    &c->lvl_cursor, &c->lvl_misc, &c->lvl_na, &c->lvl_lv, &c->lvl_cst,

@@ -1151,7 +1151,10 @@ __global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs
         // an FP64 block: the refine sweep takes all of it, in list order
         // (its clusters' runs where the sweep's are)
         const int na = a.plan->n_act;
-        for (int k = threadIdx.x; k < na; k += kWG) a.ref_idx[k] = a.idx ? a.idx[k] : k;
+        for (int k = threadIdx.x; k < na; k += kWG) {
+            a.ref_idx[k] = a.idx ? a.idx[k] : k;
+            a.ref_p[k] = k;
+        }
         if (a.n_clusters > 1)
             for (int c = threadIdx.x; c < a.n_clusters; c += kWG) ra.act_start[c] = a.act_start[c];
         __syncthreads();   // act_start complete before the plan reads it
@@ -1166,7 +1169,8 @@ __global__ void __launch_bounds__(kWG) refine_plan_kernel(SweepArgs a, SweepArgs
 }
 
 // Writes the refined sums of the flagged particles over their mixed ones
-// (a wave per particle: the refine sweep splits j into many chunks).
+// (a wave per particle: the refine sweep splits j into many chunks); for a
+// block the plan put in FP64 these are all of its particles.
 __global__ void __launch_bounds__(kWG) refine_scatter_kernel(SweepArgs a, SweepArgs ra)
 {
     const int cnt = ra.plan->n_act;
@@ -1308,6 +1312,9 @@ hipError_t launch_force(const SweepArgs& a_in, const SweepArgs* ra, int precisio
 {
     SweepArgs a = a_in;
     a.ipl = (!pot_only && (variant & 1)) ? 2 : 1;
+    // with refinement, a block the plan puts in FP64 is swept by the refine
+    // sweep's launch (the whole block as its list) and scattered from there
+    a.defer_fp64 = (!pot_only && ra && a.refine) ? 1 : 0;
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kWG), 0, st, a);
     if (marks) {
         const hipError_t e = hipEventRecord(marks[0], st);
