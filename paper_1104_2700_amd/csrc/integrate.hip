@@ -317,6 +317,37 @@ __global__ void __launch_bounds__(kWG) sel_write_plan_kernel(
     plan_body(sa, s_na);
 }
 
+// The same list without the ticket, for many blocks: a last-block ticket
+// costs a device-scope fence per block (about 65 ns each on this GPU, 0.26
+// ms at 4096 blocks), a launch about 3 us.  Every block places its entries
+// from the counts of the blocks before it, the last one publishes n_act,
+// and sel_plan_kernel plans.
+constexpr int kSelTicketMax = 48;   // selection blocks up to which the ticket is used
+
+__global__ void __launch_bounds__(kWG) sel_write_list_kernel(
+    int64_t n, const int64_t* t, const int64_t* dt, const int32_t* block_cnt, int nb,
+    const int64_t* T_in, int64_t T_end, int32_t* idx, int32_t* n_act, int64_t* counters,
+    SweepArgs sa)
+{
+    __shared__ int32_t sh[kWG];
+    __shared__ int64_t s_off[kLdsClusters];
+    const int64_t* cl_off = stage_cluster_starts(sa, s_off);
+    const int64_t T = *T_in;
+    const bool live = T <= T_end;
+    const int32_t upto = sel_write_body(n, t, dt, block_cnt, T, live, idx, sh, cl_off,
+                                        sa.n_clusters, sa.act_start, sa.act_cluster);
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+        const int32_t na = live ? upto : 0;
+        *n_act = na;
+        count_step(counters, T, na);
+    }
+}
+
+__global__ void __launch_bounds__(kWG) sel_plan_kernel(SweepArgs sa, const int32_t* n_act)
+{
+    plan_body(sa, *n_act);
+}
+
 // Stages 1-3 and the sweep plan in one workgroup, for systems that fit one
 // selection block (n <= kSelBlock): no cross-block ticket or fence, one
 // launch instead of two.  Each thread owns kSelPer consecutive particles,
@@ -1154,11 +1185,24 @@ hipError_t launch_step_select(int64_t n, const int64_t* t, const int64_t* dt, in
                            idx, n_act, T, counters, sa);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(sel_min_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min,
-                       block_cnt, nb, T, ticket + 1);
-    hipLaunchKernelGGL(sel_write_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
-                       (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
-                       counters, sa, ticket);
+    if (nb <= kSelTicketMax) {
+        hipLaunchKernelGGL(sel_min_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                           block_min, block_cnt, nb, T, ticket + 1);
+        hipLaunchKernelGGL(sel_write_plan_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                           (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
+                           counters, sa, ticket);
+    } else {
+        // many blocks: the standalone selection's passes (no tickets), the
+        // list with the clusters' runs, then the plan
+        hipLaunchKernelGGL(sel_min_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt, block_min);
+        hipLaunchKernelGGL(sel_count_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                           (const int64_t*)block_min, nb, block_cnt, T);
+        hipLaunchKernelGGL(sel_write_list_kernel, dim3(nb), dim3(kWG), 0, st, n, t, dt,
+                           (const int32_t*)block_cnt, nb, (const int64_t*)T, T_end, idx, n_act,
+                           counters, sa);
+        hipLaunchKernelGGL(sel_plan_kernel, dim3(1), dim3(kWG), 0, st, sa,
+                           (const int32_t*)n_act);
+    }
     return hipGetLastError();
 }
 

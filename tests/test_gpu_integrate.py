@@ -279,12 +279,14 @@ def _small_block_steps(H, ctx, s0, eps2, params, n):
         assert torch.equal(getattr(sc, key), getattr(sd, key)), key
 
 
-@pytest.mark.parametrize("n", [3, 3000, 6000, 20000])
+@pytest.mark.parametrize("n", [3, 3000, 6000, 20000, 200000])
 def test_lockstep_larger_systems(H, ctx, n):
     """Block steps of systems on each selection path: selection fused into
     the sweep (n = 3), one selection workgroup (n = 3000), several selection
-    blocks (n = 6000, 20000): active list, block time and corrected state
-    equal the oracle's step from the same pre-step state."""
+    blocks with the last-block ticket (n = 6000, 20000), many blocks with
+    separate passes and plan (n = 200000, 49 blocks): active list, block time
+    and corrected state equal the oracle's step from the same pre-step
+    state."""
     from oracle import oracle as O
     x, v, m, _ = _c1_setup(H, n=n, seed=31)
     eps2 = (4.0 / n) ** 2
