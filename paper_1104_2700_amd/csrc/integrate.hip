@@ -910,46 +910,72 @@ __device__ int64_t quantize_dt(double crit, int k_old, int64_t T, int tick_bits,
 }
 
 // ---- corrector + next step (procedure steps 5-8) -------------------------
-// a1, j1: the new acceleration and jerk of active position p.
-__device__ void correct_one(const CorrectArgs& c, int p, int64_t T, const double a1v[3],
-                            const double j1v[3], double pot1, bool have_pot)
+// The pre-step state of an active particle that the corrector reads, loaded
+// before the new forces are summed so that these loads overlap the sum's.
+struct OldState {
+    int i;                      // particle index
+    int64_t t, dt;
+    double x[3], v[3];          // x, v (prediction in place) or xp, vp
+    double a[3], j[3];
+};
+
+__device__ __forceinline__ void load_old(const CorrectArgs& c, int p, OldState& o)
 {
     const int64_t n = c.n;
     const int i = c.idx ? c.idx[p] : p;
+    o.i = i;
+    o.dt = c.dt[i];
+    o.t = c.t[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t q = d * n + i;
+        o.x[d] = c.predict_i ? c.x[q] : c.xp[q];
+        o.v[d] = c.predict_i ? c.v[q] : c.vp[q];
+        o.a[d] = c.a[q];
+        o.j[d] = c.j[q];
+    }
+}
+
+// a1, j1: the new acceleration and jerk of active position p, whose
+// pre-step state is o.
+__device__ void correct_one(const CorrectArgs& c, int p, const OldState& o, int64_t T,
+                            const double a1v[3], const double j1v[3], double pot1, bool have_pot)
+{
+    const int64_t n = c.n;
+    const int i = o.i;
     const double tick = ldexp(1.0, -c.tick_bits);
-    const int64_t dt_old = c.dt[i];
+    const int64_t dt_old = o.dt;
     const double h = (double)dt_old * tick;
     const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
     double s1[3], cc[3], xp[3], vp[3];
     if (c.predict_i) {
         // equations (xpred), (vpred) for this particle, dt = T - t_i
-        const double hp = (double)(T - c.t[i]) * tick;
+        const double hp = (double)(T - o.t) * tick;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const int64_t o = d * n + i;
-            const double ac = c.a[o], jk = c.j[o];
-            xp[d] = fma(hp, fma(hp, fma(hp, jk * (1.0 / 6.0), ac * 0.5), c.v[o]), c.x[o]);
-            vp[d] = fma(hp, fma(hp, jk * 0.5, ac), c.v[o]);
+            const double ac = o.a[d], jk = o.j[d];
+            xp[d] = fma(hp, fma(hp, fma(hp, jk * (1.0 / 6.0), ac * 0.5), o.v[d]), o.x[d]);
+            vp[d] = fma(hp, fma(hp, jk * 0.5, ac), o.v[d]);
         }
     } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            xp[d] = c.xp[d * n + i];
-            vp[d] = c.vp[d * n + i];
+            xp[d] = o.x[d];
+            vp[d] = o.v[d];
         }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int64_t o = d * n + i;
-        const double a0 = c.a[o], j0 = c.j[o];
+        const int64_t q = d * n + i;
+        const double a0 = o.a[d], j0 = o.j[d];
         const double a1 = a1v[d], j1 = j1v[d];
         const double da = a0 - a1;
         const double s0 = 2.0 * (-3.0 * da - (2.0 * j0 + j1) * h) / h2;
         const double c0 = 6.0 * (2.0 * da + (j0 + j1) * h) / h3;
-        c.x[o] = xp[d] + s0 * h4 / 24.0 + c0 * h5 / 120.0;
-        c.v[o] = vp[d] + s0 * h3 / 6.0 + c0 * h4 / 24.0;
-        c.a[o] = a1;
-        c.j[o] = j1;
+        c.x[q] = xp[d] + s0 * h4 / 24.0 + c0 * h5 / 120.0;
+        c.v[q] = vp[d] + s0 * h3 / 6.0 + c0 * h4 / 24.0;
+        c.a[q] = a1;
+        c.j[q] = j1;
         s1[d] = fma(c0, h, s0);
         cc[d] = c0;
     }
@@ -977,13 +1003,15 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
     if (p >= na) return;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     const int64_t st = c.n_act_max;
+    OldState o;
+    load_old(c, p, o);
     double a1[3], j1[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         a1[d] = c.acc1[d * st + p];
         j1[d] = c.jrk1[d * st + p];
     }
-    correct_one(c, p, T, a1, j1, c.pot1 ? c.pot1[p] : 0.0, c.pot1 != nullptr);
+    correct_one(c, p, o, T, a1, j1, c.pot1 ? c.pot1[p] : 0.0, c.pot1 != nullptr);
 }
 
 // The block-step corrector: sums the sweep's j-chunk partials of position p
@@ -995,22 +1023,26 @@ __device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, i
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     if (thread_reduce(sa.plan->s_max, na)) {
         for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
+            OldState o;
+            load_old(c, p, o);
             double s[kRows];
             reduce_partials(sa, na, p, s);
             const double a1[3] = {s[0], s[1], s[2]};
             const double j1[3] = {s[3], s[4], s[5]};
-            correct_one(c, p, T, a1, j1, s[6], true);
+            correct_one(c, p, o, T, a1, j1, s[6], true);
         }
     } else {
         const int lane = threadIdx.x & 63;
         const int wpb = kWG / 64;
         for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
+            OldState o;
+            load_old(c, p, o);   // the same address in every lane of the wave
             double s[kRows];
             reduce_partials_wave(sa, na, p, lane, s);
             if (lane == 0) {
                 const double a1[3] = {s[0], s[1], s[2]};
                 const double j1[3] = {s[3], s[4], s[5]};
-                correct_one(c, p, T, a1, j1, s[6], true);
+                correct_one(c, p, o, T, a1, j1, s[6], true);
             }
         }
     }
@@ -1046,7 +1078,9 @@ __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, Swee
         const int p = base + lane;
         const int k = p < na ? ra.ref_pos[p] : -1;
         double a1[3], j1[3], pot1 = 0.0;
+        OldState o;
         if (p < na) {
+            load_old(c, p, o);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 a1[d] = c.acc1[d * st + p];
@@ -1067,7 +1101,7 @@ __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, Swee
                 pot1 = s[6];
             }
         }
-        if (p < na) correct_one(c, p, T, a1, j1, pot1, true);
+        if (p < na) correct_one(c, p, o, T, a1, j1, pot1, true);
     }
 }
 
