@@ -464,10 +464,12 @@ __device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, i
         ea += xa;
         ej += xj;
     }
+    // every row takes each butterfly step together (independent reads
+    // issued back to back)
 #pragma unroll
-    for (int q = 0; q < kRows - 1; ++q)
-        for (int o = 1; o < 64; o <<= 1) out[q] += __shfl_xor(out[q], o);
     for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < kRows - 1; ++q) out[q] += __shfl_xor(out[q], o);
         ea += __shfl_xor(ea, o);
         ej += __shfl_xor(ej, o);
     }

@@ -724,18 +724,6 @@ __device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L
         });
 }
 
-__device__ __forceinline__ double shfl_sum(double v, int L)
-{
-    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ float shfl_sum_f(float v, int L)
-{
-    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // Final per-lane values: acc xyz, jerk xyz, pot (-sum m/r); the error
 // estimates are combined separately (they are FP32).
 __device__ __forceinline__ void finalize(const SumD& S, double out[kRows])
@@ -1020,37 +1008,54 @@ sweep_kernel(SweepArgs a)
             }
         }
 
+        // the L lanes of a particle combine their sums by an xor butterfly;
+        // every row of every particle of the lane takes each butterfly step
+        // together, so a step's cross-lane reads are issued back to back
+        // (one row after another, they were a chain of ~170 dependent reads)
+        double out[IPL][kRows];
+        float ea[IPL], ej[IPL];
+        float fj[IPL][3];   // the paper-faithful mode's FP32 jerk sums
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
-            double out[kRows];
-            finalize(S[q], out);
-            float ea = S[q].ea, ej = S[q].ej;
-            if (L > 1) {
-#pragma unroll
-                for (int r = 0; r < 7; ++r) out[r] = shfl_sum(out[r], L);
-                ea = shfl_sum_f(ea, L);
-                ej = shfl_sum_f(ej, L);
-            }
-            out[kRows - 1] = pack_est(ea, ej);
+            finalize(S[q], out[q]);
+            ea[q] = S[q].ea;
+            ej[q] = S[q].ej;
             if constexpr (PREC == 3) {
                 // the jerk: one FP32 running sum per lane over every L-th j of
                 // the whole range (the plan gives this mode one j-chunk), the
                 // L lanes' sums added in FP32 too; near pairs, if any, in FP64
-                float fj[3] = {F[q].jx, F[q].jy, F[q].jz};
-                if (L > 1) {
+                fj[q][0] = F[q].jx;
+                fj[q][1] = F[q].jy;
+                fj[q][2] = F[q].jz;
+            }
+        }
+        for (int o = 1; o < L; o <<= 1) {
 #pragma unroll
-                    for (int r = 0; r < 3; ++r) fj[r] = shfl_sum_f(fj[r], L);
+            for (int q = 0; q < IPL; ++q) {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) out[q][r] += __shfl_xor(out[q][r], o);
+                ea[q] += __shfl_xor(ea[q], o);
+                ej[q] += __shfl_xor(ej[q], o);
+                if constexpr (PREC == 3) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) fj[q][r] += __shfl_xor(fj[q][r], o);
                 }
+            }
+        }
 #pragma unroll
-                for (int r = 0; r < 3; ++r) out[3 + r] += (double)fj[r];
+        for (int q = 0; q < IPL; ++q) {
+            out[q][kRows - 1] = pack_est(ea[q], ej[q]);
+            if constexpr (PREC == 3) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) out[q][3 + r] += (double)fj[q][r];
             }
             if (valid[q] && sub == 0) {
                 double* dst = a.partial + (int64_t)k * kRows * na + pp[q];
                 if (POT_ONLY) {
-                    dst[6 * (int64_t)na] = out[6];
+                    dst[6 * (int64_t)na] = out[q][6];
                 } else {
 #pragma unroll
-                    for (int r = 0; r < kRows; ++r) dst[r * (int64_t)na] = out[r];
+                    for (int r = 0; r < kRows; ++r) dst[r * (int64_t)na] = out[q][r];
                 }
             }
         }
