@@ -238,7 +238,10 @@ def test_force_jerk_timed_matches_and_times(H, ctx):
 def test_mixed_ensemble_straddling_threshold(H, ctx):
     """An ensemble whose clusters straddle fp64_below (set to 8192 here)
     runs two kernels: the small clusters' sums equal the FP64 sweep's bit
-    for bit, the large ones meet the mixed bar against the oracle."""
+    for bit, the large ones meet the mixed bar against the oracle.  A small
+    block of the same ensemble (below 5e7 interactions) is swept in FP64
+    altogether, through the refine sweep's launch: every active particle's
+    sums equal the FP64 sweep's bit for bit."""
     from oracle import oracle as O
     from paper_1104_2700_amd import inputs
     sizes = [300, 9000, 1000, 12000, 64]
@@ -253,13 +256,17 @@ def test_mixed_ensemble_straddling_threshold(H, ctx):
     s = H.State(x, v, m)
     s.xp.copy_(s.x); s.vp.copy_(s.v)
     A64, J64, P64 = ctx.force_jerk(s, None, 0.0, H.FP64, clusters=cl)
+    small = torch.arange(7, int(off[-1]), 200, dtype=torch.int32, device="cuda")
+    S64 = ctx.force_jerk(s, small, 0.0, H.FP64, clusters=cl)
     saved = ctx.get_mixed_policy(H.MIXED)
     ctx.set_mixed_policy(H.MIXED, saved[0], 8192)
     try:
         A, J, P = ctx.force_jerk(s, None, 0.0, H.MIXED, clusters=cl)
+        Sm = ctx.force_jerk(s, small, 0.0, H.MIXED, clusters=cl)
         torch.cuda.synchronize()
     finally:
         ctx.set_mixed_policy(H.MIXED, *saved)
+    assert all(torch.equal(Sm[q], S64[q]) for q in range(3))
     for c, nc in enumerate(sizes):
         lo, hi = off[c], off[c + 1]
         if nc < 8192:
