@@ -255,13 +255,39 @@ def test_mixed_small_block_steps_take_fp64(H, ctx):
         ctx.set_mixed_policy(H.MIXED, *saved)
 
 
-def _small_block_steps(H, ctx, s0, eps2, params, n):
+def test_mixed_small_block_steps_take_fp64_ensemble(H, ctx):
+    """The same for an ensemble whose clusters straddle fp64_below (8192
+    here): small blocks are swept in FP64 through the refine sweep's launch
+    and reduced by the corrector, so the state follows FP64 steps bit for
+    bit, in hermite_step and hermite_run."""
+    from paper_1104_2700_amd import inputs
+    sizes = [300, 9000, 1000, 12000, 64]
+    xs, vs, ms = [], [], []
+    for c, nc in enumerate(sizes):
+        x, v, m = inputs.plummer(nc, 700 + c)
+        xs.append(x); vs.append(v); ms.append(m)
+    x = np.concatenate(xs, 1); v = np.concatenate(vs, 1); m = np.concatenate(ms)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cl = H.Clusters(off, (4.0 / np.maximum(np.array(sizes, float), 64)) ** 2)
+    params = H.dt_params(0.02, H.DT_PAPER, 3, 20)
+    s0 = H.State(x, v, m, TB)
+    ctx.initialize(s0, 0.0, params, H.FP64, clusters=cl)
+    saved = ctx.get_mixed_policy(H.MIXED)
+    ctx.set_mixed_policy(H.MIXED, saved[0], 8192)
+    try:
+        _small_block_steps(H, ctx, s0, 0.0, params, max(sizes), clusters=cl)
+    finally:
+        ctx.set_mixed_policy(H.MIXED, *saved)
+
+
+def _small_block_steps(H, ctx, s0, eps2, params, n, clusters=None):
+    """n: the largest system, so that n_act * n bounds a block's interactions."""
     sa, sb = s0.clone(), s0.clone()
     checked = 0
     for k in range(16):
-        ctx.step(sa, eps2, params, H.FP64)
+        ctx.step(sa, eps2, params, H.FP64, clusters=clusters)
         na = ctx.counters()["n_act"]
-        ctx.step(sb, eps2, params, H.MIXED)
+        ctx.step(sb, eps2, params, H.MIXED, clusters=clusters)
         torch.cuda.synchronize()
         if na * n >= 50000000:
             break
@@ -270,10 +296,10 @@ def _small_block_steps(H, ctx, s0, eps2, params, n):
         checked += 1
     assert checked >= 8
     sc = s0.clone()
-    ctx.run(sc, eps2, params, 1 << (TB - 3), H.MIXED, max_steps=checked)
+    ctx.run(sc, eps2, params, 1 << (TB - 3), H.MIXED, max_steps=checked, clusters=clusters)
     sd = s0.clone()
     for k in range(checked):
-        ctx.step(sd, eps2, params, H.FP64)
+        ctx.step(sd, eps2, params, H.FP64, clusters=clusters)
     torch.cuda.synchronize()
     for key in ("x", "v", "a", "j", "pot", "t", "dt"):
         assert torch.equal(getattr(sc, key), getattr(sd, key)), key
