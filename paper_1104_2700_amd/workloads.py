@@ -130,7 +130,10 @@ def block_run(ctx, s, eps2, params, t_end, precision, clusters=None,
         "E0": float(e0.sum()) if e0.size == 1 else None,
         "active_size_histogram_log2": {("0" if b == 0 else "[2^%d,2^%d)" % (b - 1, b)): v
                                        for b, v in enumerate(hist) if v},
-        "mean_active": inter / max(steps, 1) / (s.n if clusters is None else 1),
+        # one system: interactions / (steps * n) is the mean block size; an
+        # ensemble's interactions weight each cluster's block by its size
+        "mean_active": inter / max(steps, 1) / s.n if clusters is None else None,
+        "mean_interactions_per_step": inter / max(steps, 1),
     }
 
 
