@@ -919,10 +919,9 @@ struct OldState {
     double a[3], j[3];
 };
 
-__device__ __forceinline__ void load_old(const CorrectArgs& c, int p, OldState& o)
+__device__ __forceinline__ void load_old_i(const CorrectArgs& c, int i, OldState& o)
 {
     const int64_t n = c.n;
-    const int i = c.idx ? c.idx[p] : p;
     o.i = i;
     o.dt = c.dt[i];
     o.t = c.t[i];
@@ -934,6 +933,11 @@ __device__ __forceinline__ void load_old(const CorrectArgs& c, int p, OldState& 
         o.a[d] = c.a[q];
         o.j[d] = c.j[q];
     }
+}
+
+__device__ __forceinline__ void load_old(const CorrectArgs& c, int p, OldState& o)
+{
+    load_old_i(c, c.idx ? c.idx[p] : p, o);
 }
 
 // a1, j1: the new acceleration and jerk of active position p, whose
@@ -1017,16 +1021,40 @@ __global__ void __launch_bounds__(kWG) correct_kernel(CorrectArgs c)
 // The block-step corrector: sums the sweep's j-chunk partials of position p
 // in fixed order (the reduce stage) and corrects in the same kernel.
 // Grid-stride: a thread per particle for few chunks, a wave for many.
-__device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, int na)
+// The particle index (and, for ensembles, the cluster) of a thread's or a
+// wave's first position, loaded together with the plan: neither depends on
+// it, and the first position's state and partial sums then need one round
+// trip after the plan instead of two.
+struct FirstPos {
+    int p, i, cl;   // cl: the cluster from the selection's record, or -1
+};
+
+__device__ __forceinline__ FirstPos first_pos(const CorrectArgs& c, const SweepArgs& sa, int p)
+{
+    const int q = p < c.n_act_max ? p : c.n_act_max - 1;
+    FirstPos f;
+    f.p = p;
+    f.i = c.idx ? c.idx[q] : q;
+    f.cl = (sa.n_clusters > 1 && sa.act_cluster) ? sa.act_cluster[q] : -1;
+    return f;
+}
+
+__device__ __forceinline__ int first_chunks(const SweepArgs& sa, const FirstPos& f, int p)
+{
+    return (p == f.p && f.cl >= 0) ? sa.chunks[f.cl] : chunks_of(sa, p);
+}
+
+__device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, int na,
+                                    FirstPos ft, FirstPos fw)
 {
     if (c.na_seen && blockIdx.x == 0 && threadIdx.x == 0) *c.na_seen = na;
     const int64_t T = c.T_dev ? *c.T_dev : c.T_host;
     if (thread_reduce(sa.plan->s_max, na)) {
-        for (int p = blockIdx.x * kWG + threadIdx.x; p < na; p += gridDim.x * kWG) {
+        for (int p = ft.p; p < na; p += gridDim.x * kWG) {
             OldState o;
-            load_old(c, p, o);
+            load_old_i(c, p == ft.p ? ft.i : (c.idx ? c.idx[p] : p), o);
             double s[kRows];
-            reduce_partials(sa, na, p, s);
+            reduce_partials_ch(sa, na, p, first_chunks(sa, ft, p), s);
             const double a1[3] = {s[0], s[1], s[2]};
             const double j1[3] = {s[3], s[4], s[5]};
             correct_one(c, p, o, T, a1, j1, s[6], true);
@@ -1034,11 +1062,12 @@ __device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, i
     } else {
         const int lane = threadIdx.x & 63;
         const int wpb = kWG / 64;
-        for (int p = blockIdx.x * wpb + (int)(threadIdx.x >> 6); p < na; p += gridDim.x * wpb) {
+        for (int p = fw.p; p < na; p += gridDim.x * wpb) {
             OldState o;
-            load_old(c, p, o);   // the same address in every lane of the wave
+            // the same address in every lane of the wave
+            load_old_i(c, p == fw.p ? fw.i : (c.idx ? c.idx[p] : p), o);
             double s[kRows];
-            reduce_partials_wave(sa, na, p, lane, s);
+            reduce_partials_wave_ch(sa, na, p, first_chunks(sa, fw, p), lane, s);
             if (lane == 0) {
                 const double a1[3] = {s[0], s[1], s[2]};
                 const double j1[3] = {s[3], s[4], s[5]};
@@ -1048,9 +1077,16 @@ __device__ void correct_reduce_body(const CorrectArgs& c, const SweepArgs& sa, i
     }
 }
 
+__device__ __forceinline__ void correct_reduce_entry(const CorrectArgs& c, const SweepArgs& sa)
+{
+    const FirstPos ft = first_pos(c, sa, blockIdx.x * kWG + (int)threadIdx.x);
+    const FirstPos fw = first_pos(c, sa, blockIdx.x * (kWG / 64) + (int)(threadIdx.x >> 6));
+    correct_reduce_body(c, sa, sa.plan->n_act, ft, fw);
+}
+
 __global__ void __launch_bounds__(kWG) correct_reduce_kernel(CorrectArgs c, SweepArgs sa)
 {
-    correct_reduce_body(c, sa, sa.plan->n_act);
+    correct_reduce_entry(c, sa);
 }
 
 // The block-step corrector of a refined mixed sweep: the mixed sums from
@@ -1062,7 +1098,7 @@ __global__ void __launch_bounds__(kWG) correct_refine_kernel(CorrectArgs c, Swee
                                                              SweepArgs ra)
 {
     if (a.plan->fp64_all) {
-        correct_reduce_body(c, ra, ra.plan->n_act);
+        correct_reduce_entry(c, ra);
         return;
     }
     const int na = *c.n_act_dev;

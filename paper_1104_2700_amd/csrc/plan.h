@@ -418,9 +418,15 @@ __device__ __forceinline__ void unpack_est(double d, float* ea, float* ej)
 // a sum that started at +0.0 unchanged bit for bit).
 constexpr int kReduceBatch = 4;
 
-__device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[kRows])
+// j-chunks of active position p (its cluster's).
+__device__ inline int chunks_of(const SweepArgs& a, int p)
 {
-    const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
+    return a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
+}
+
+__device__ inline void reduce_partials_ch(const SweepArgs& a, int na, int p, int ch,
+                                          double out[kRows])
+{
 #pragma unroll
     for (int q = 0; q < kRows; ++q) out[q] = 0.0;
     float ea = 0.0f, ej = 0.0f;
@@ -449,10 +455,14 @@ __device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double
 // The same sum by a whole wave (for many chunks): lane l adds chunks
 // l, l + 64, ... in order, then a fixed xor butterfly combines the lanes.
 // Every lane returns the total.  Deterministic for a given chunk count.
-__device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, int lane,
-                                            double out[kRows])
+__device__ inline void reduce_partials(const SweepArgs& a, int na, int p, double out[kRows])
 {
-    const int ch = a.n_clusters <= 1 ? a.plan->s_max : a.chunks[cluster_of(a, p)];
+    reduce_partials_ch(a, na, p, chunks_of(a, p), out);
+}
+
+__device__ inline void reduce_partials_wave_ch(const SweepArgs& a, int na, int p, int ch,
+                                               int lane, double out[kRows])
+{
 #pragma unroll
     for (int q = 0; q < kRows; ++q) out[q] = 0.0;
     float ea = 0.0f, ej = 0.0f;
@@ -474,6 +484,12 @@ __device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, i
         ej += __shfl_xor(ej, o);
     }
     out[kRows - 1] = pack_est(ea, ej);
+}
+
+__device__ inline void reduce_partials_wave(const SweepArgs& a, int na, int p, int lane,
+                                            double out[kRows])
+{
+    reduce_partials_wave_ch(a, na, p, chunks_of(a, p), lane, out);
 }
 
 // Position and velocity of particle i for the sweep: predicted on the fly
