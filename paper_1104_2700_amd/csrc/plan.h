@@ -452,6 +452,50 @@ __device__ inline void reduce_partials_ch(const SweepArgs& a, int na, int p, int
     out[kRows - 1] = pack_est(ea, ej);
 }
 
+// The partner's value in step O of a butterfly in which the lanes of each
+// aligned group of 2 O add their values (every lane ends with the group's
+// sum).  Within a 16-lane row the partner comes through a DPP lane move:
+// quad permutes for O = 1, 2, then the half-row and row mirrors for O = 4, 8.
+// After the earlier steps all lanes of a quad (of a half-row) hold the same
+// value, so the mirror partner gives bit for bit the xor partner's sum.
+// Across rows (O = 16, 32) it goes through ds_bpermute.
+template <int O>
+__device__ __forceinline__ int lane_partner_i32(int v)
+{
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "DPP steps");
+    constexpr int kCtrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int O>
+__device__ __forceinline__ double lane_partner(double v)
+{
+    if constexpr (O >= 16) {
+        return __shfl_xor(v, O);
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = lane_partner_i32<O>((int)b);
+        const int hi = lane_partner_i32<O>((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+    }
+}
+
+template <int O>
+__device__ __forceinline__ float lane_partner(float v)
+{
+    if constexpr (O >= 16) return __shfl_xor(v, O);
+    else return __int_as_float(lane_partner_i32<O>(__float_as_int(v)));
+}
+
+template <int O>
+__device__ __forceinline__ void wave_sum_step(double* out, float& ea, float& ej)
+{
+#pragma unroll
+    for (int q = 0; q < kRows - 1; ++q) out[q] += lane_partner<O>(out[q]);
+    ea += lane_partner<O>(ea);
+    ej += lane_partner<O>(ej);
+}
+
 // The same sum by a whole wave (for many chunks): lane l adds chunks
 // l, l + 64, ... in order, then a fixed xor butterfly combines the lanes.
 // Every lane returns the total.  Deterministic for a given chunk count.
@@ -476,13 +520,12 @@ __device__ inline void reduce_partials_wave_ch(const SweepArgs& a, int na, int p
     }
     // every row takes each butterfly step together (independent reads
     // issued back to back)
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-        for (int q = 0; q < kRows - 1; ++q) out[q] += __shfl_xor(out[q], o);
-        ea += __shfl_xor(ea, o);
-        ej += __shfl_xor(ej, o);
-    }
+    wave_sum_step<1>(out, ea, ej);
+    wave_sum_step<2>(out, ea, ej);
+    wave_sum_step<4>(out, ea, ej);
+    wave_sum_step<8>(out, ea, ej);
+    wave_sum_step<16>(out, ea, ej);
+    wave_sum_step<32>(out, ea, ej);
     out[kRows - 1] = pack_est(ea, ej);
 }
 

@@ -724,6 +724,26 @@ __device__ __forceinline__ void tile_sp(const TileSP& T, int cnt, int sub, int L
         });
 }
 
+// One step of the L lanes' butterfly (see lane_partner) for all seven rows,
+// both error estimates and, in the paper-faithful mode, the FP32 jerk sums
+// of every particle of the lane.
+template <int O, int IPL, bool SP>
+__device__ __forceinline__ void lanes_sum_step(double (&out)[IPL][kRows], float (&ea)[IPL],
+                                               float (&ej)[IPL], float (&fj)[IPL][3])
+{
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+#pragma unroll
+        for (int r = 0; r < 7; ++r) out[q][r] += lane_partner<O>(out[q][r]);
+        ea[q] += lane_partner<O>(ea[q]);
+        ej[q] += lane_partner<O>(ej[q]);
+        if constexpr (SP) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) fj[q][r] += lane_partner<O>(fj[q][r]);
+        }
+    }
+}
+
 // Final per-lane values: acc xyz, jerk xyz, pot (-sum m/r); the error
 // estimates are combined separately (they are FP32).
 __device__ __forceinline__ void finalize(const SumD& S, double out[kRows])
@@ -1029,19 +1049,12 @@ sweep_kernel(SweepArgs a)
                 fj[q][2] = F[q].jz;
             }
         }
-        for (int o = 1; o < L; o <<= 1) {
-#pragma unroll
-            for (int q = 0; q < IPL; ++q) {
-#pragma unroll
-                for (int r = 0; r < 7; ++r) out[q][r] += __shfl_xor(out[q][r], o);
-                ea[q] += __shfl_xor(ea[q], o);
-                ej[q] += __shfl_xor(ej[q], o);
-                if constexpr (PREC == 3) {
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) fj[q][r] += __shfl_xor(fj[q][r], o);
-                }
-            }
-        }
+        if (L > 1) lanes_sum_step<1, IPL, PREC == 3>(out, ea, ej, fj);
+        if (L > 2) lanes_sum_step<2, IPL, PREC == 3>(out, ea, ej, fj);
+        if (L > 4) lanes_sum_step<4, IPL, PREC == 3>(out, ea, ej, fj);
+        if (L > 8) lanes_sum_step<8, IPL, PREC == 3>(out, ea, ej, fj);
+        if (L > 16) lanes_sum_step<16, IPL, PREC == 3>(out, ea, ej, fj);
+        if (L > 32) lanes_sum_step<32, IPL, PREC == 3>(out, ea, ej, fj);
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
             out[q][kRows - 1] = pack_est(ea[q], ej[q]);
