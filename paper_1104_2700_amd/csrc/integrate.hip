@@ -30,10 +30,7 @@ __device__ __forceinline__ int64_t next_time(const int64_t* t, const int64_t* dt
 // per level.
 __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* s)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t u = __shfl_xor(v, o);
-        v = u < v ? u : v;
-    }
+    v = wave_min_i64(v);
     __syncthreads();                     // s may still be read by a previous call
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -44,7 +41,7 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* s)
 
 __device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* s)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v = wave_sum_i32(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -57,11 +54,7 @@ __device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* s)
 __device__ __forceinline__ int32_t block_exscan_i32(int32_t v, int32_t* s, int32_t* total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
+    const int32_t x = wave_inscan(v);
     __syncthreads();
     if (lane == 63) s[wave] = x;
     __syncthreads();
@@ -373,10 +366,7 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
         v = e[r] < v ? e[r] : v;
     }
     // block minimum: wave butterfly, then the kWaves wave minima
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t u = __shfl_xor(v, o);
-        v = u < v ? u : v;
-    }
+    v = wave_min_i64(v);
     if (lane == 0) s_min[wave] = v;
     __syncthreads();
     int64_t T = s_min[0];
@@ -386,11 +376,7 @@ __global__ void __launch_bounds__(kWG) sel_single_plan_kernel(
 #pragma unroll
     for (int r = 0; r < kSelPer; ++r) c += (e[r] == T) ? 1 : 0;
     // ascending positions: inclusive wave scan, then the wave offsets
-    int32_t x = c;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
+    const int32_t x = wave_inscan(c);
     if (lane == 63) s_cnt[wave] = x;
     __syncthreads();
     int32_t off = 0, total = 0;
@@ -472,11 +458,7 @@ __global__ void __launch_bounds__(kWG) level_build_kernel(LevelArgs L)
         // this block's place in every step size: the sizes before it, then
         // the blocks that claimed that size before it
         const int32_t c = L.cnt[tid];
-        int32_t x = c;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t u = __shfl_up(x, o);
-            if (tid >= o) x += u;
-        }
+        const int32_t x = wave_inscan(c);
         const int32_t mine = h[tid];
         base[tid] = x - c + (mine > 0 ? atomicAdd(&L.cursor[tid], mine) : 0);
         h[tid] = 0;
@@ -539,12 +521,7 @@ __device__ __forceinline__ bool level_put(const LevelArgs& L, int32_t* out, int3
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int32_t wave_inscan_i32(int32_t x)
 {
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
-    return x;
+    return wave_inscan(x);
 }
 
 struct LevelLds {
@@ -639,8 +616,7 @@ __device__ __forceinline__ int64_t level_next(int32_t cnt_b, int64_t Tlast, int6
         const int bmin = __builtin_ctzll(occ);
         Tn = ((Tlast >> bmin) + 1) << bmin;
         const int zn = __builtin_ctzll((unsigned long long)Tn);
-        v = lane <= zn ? cnt_b : 0;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        v = wave_sum_i32(lane <= zn ? cnt_b : 0);
     }
     *na = Tn > T_end ? 0 : v;
     return Tn;

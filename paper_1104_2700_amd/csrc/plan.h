@@ -7,6 +7,117 @@
 
 namespace hm {
 
+// ---- wave-level primitives (every lane of the wave must call them) ----
+// The partner's value in step O of a butterfly in which the lanes of each
+// aligned group of 2 O combine their values (every lane ends with the
+// group's result).  Within a 16-lane row the partner comes through a DPP
+// lane move: quad permutes for O = 1, 2, then the half-row and row mirrors
+// for O = 4, 8.  After the earlier steps all lanes of a quad (of a half-row)
+// hold the same value, so the mirror partner gives bit for bit the xor
+// partner's result (steps must run in ascending O).  Across rows (O = 16,
+// 32) the value goes through ds_bpermute.
+template <int O>
+__device__ __forceinline__ int lane_partner_i32(int v)
+{
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "DPP steps");
+    constexpr int kCtrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int O>
+__device__ __forceinline__ int32_t lane_xor(int32_t v)
+{
+    if constexpr (O >= 16) return __shfl_xor(v, O);
+    else return lane_partner_i32<O>(v);
+}
+
+template <int O>
+__device__ __forceinline__ int64_t lane_xor(int64_t v)
+{
+    if constexpr (O >= 16) {
+        return __shfl_xor(v, O);
+    } else {
+        const int lo = lane_partner_i32<O>((int)v);
+        const int hi = lane_partner_i32<O>((int)(v >> 32));
+        return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+    }
+}
+
+template <int O>
+__device__ __forceinline__ double lane_partner(double v)
+{
+    return __longlong_as_double((long long)lane_xor<O>((int64_t)__double_as_longlong(v)));
+}
+
+template <int O>
+__device__ __forceinline__ float lane_partner(float v)
+{
+    return __int_as_float(lane_xor<O>((int32_t)__float_as_int(v)));
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
+{
+    v += lane_xor<1>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<8>(v);
+    v += lane_xor<16>(v);
+    v += lane_xor<32>(v);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    v += lane_xor<1>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<8>(v);
+    v += lane_xor<16>(v);
+    v += lane_xor<32>(v);
+    return v;
+}
+
+__device__ __forceinline__ int64_t min_i64(int64_t a, int64_t b) { return b < a ? b : a; }
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+    v = min_i64(v, lane_xor<1>(v));
+    v = min_i64(v, lane_xor<2>(v));
+    v = min_i64(v, lane_xor<4>(v));
+    v = min_i64(v, lane_xor<8>(v));
+    v = min_i64(v, lane_xor<16>(v));
+    v = min_i64(v, lane_xor<32>(v));
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v)
+{
+    int32_t u;
+    u = lane_xor<1>(v);  v = u > v ? u : v;
+    u = lane_xor<2>(v);  v = u > v ? u : v;
+    u = lane_xor<4>(v);  v = u > v ? u : v;
+    u = lane_xor<8>(v);  v = u > v ? u : v;
+    u = lane_xor<16>(v); v = u > v ? u : v;
+    u = lane_xor<32>(v); v = u > v ? u : v;
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave, by DPP lane moves:
+// within each 16-lane row every lane adds the lanes 1, 2, 4 and 8 below it
+// (zero past the row's start), then rows 1 and 3 add the last lane of the
+// row below and rows 2 and 3 the last lane of row 1.
+__device__ __forceinline__ int32_t wave_inscan(int32_t x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
+
 template <typename T>
 __device__ inline int upper_bound_i64(const int64_t* a, int count, T key)
 {
@@ -90,10 +201,7 @@ __device__ inline int32_t select_in_lds(const int64_t* t, const int64_t* dt, int
         e[r] = i < n ? x : INT64_MAX;
         v = e[r] < v ? e[r] : v;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t u = __shfl_xor(v, o);
-        v = u < v ? u : v;
-    }
+    v = wave_min_i64(v);
     if (lane == 0) s_min[wave] = v;
     __syncthreads();
     int64_t T = s_min[0];
@@ -101,11 +209,7 @@ __device__ inline int32_t select_in_lds(const int64_t* t, const int64_t* dt, int
     int32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kPer; ++r) c += e[r] == T ? 1 : 0;
-    int32_t x = c;                      // inclusive scan over the wave
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
+    const int32_t x = wave_inscan(c);   // inclusive scan over the wave
     if (lane == 63) s_cnt[wave] = x;
     __syncthreads();
     int32_t pos = x - c, total = 0;
@@ -197,11 +301,7 @@ __device__ inline int32_t block_exscan(int32_t v, int32_t* total)
     __shared__ int32_t s_w[kWG / 64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
+    const int32_t x = wave_inscan(v);
     if (lane == 63) s_w[wave] = x;
     __syncthreads();
     int32_t off = x - v, tot = 0;
@@ -225,18 +325,9 @@ __device__ inline int32_t block_exscan_sum_max(int32_t v, int32_t* total, int64_
     __shared__ int32_t s_m[kWG / 64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(x, o);
-        if (lane >= o) x += u;
-    }
-    int64_t sv = *sum;
-    int32_t m = *mx;
-    for (int o = 32; o > 0; o >>= 1) {
-        sv += __shfl_xor(sv, o);
-        const int32_t u = __shfl_xor(m, o);
-        m = u > m ? u : m;
-    }
+    const int32_t x = wave_inscan(v);
+    int64_t sv = wave_sum_i64(*sum);
+    int32_t m = wave_max_i32(*mx);
     if (lane == 63) {
         s_w[wave] = x;
         s_s[wave] = sv;
@@ -450,41 +541,6 @@ __device__ inline void reduce_partials_ch(const SweepArgs& a, int na, int p, int
         }
     }
     out[kRows - 1] = pack_est(ea, ej);
-}
-
-// The partner's value in step O of a butterfly in which the lanes of each
-// aligned group of 2 O add their values (every lane ends with the group's
-// sum).  Within a 16-lane row the partner comes through a DPP lane move:
-// quad permutes for O = 1, 2, then the half-row and row mirrors for O = 4, 8.
-// After the earlier steps all lanes of a quad (of a half-row) hold the same
-// value, so the mirror partner gives bit for bit the xor partner's sum.
-// Across rows (O = 16, 32) it goes through ds_bpermute.
-template <int O>
-__device__ __forceinline__ int lane_partner_i32(int v)
-{
-    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "DPP steps");
-    constexpr int kCtrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
-    return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
-}
-
-template <int O>
-__device__ __forceinline__ double lane_partner(double v)
-{
-    if constexpr (O >= 16) {
-        return __shfl_xor(v, O);
-    } else {
-        const long long b = __double_as_longlong(v);
-        const int lo = lane_partner_i32<O>((int)b);
-        const int hi = lane_partner_i32<O>((int)(b >> 32));
-        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
-    }
-}
-
-template <int O>
-__device__ __forceinline__ float lane_partner(float v)
-{
-    if constexpr (O >= 16) return __shfl_xor(v, O);
-    else return __int_as_float(lane_partner_i32<O>(__float_as_int(v)));
 }
 
 template <int O>
