@@ -296,6 +296,46 @@ __host__ __device__ inline void plan_split(const SweepArgs& a, int32_t na, int64
     *jc_out = jc;
 }
 
+// The same split evaluated by a wave (lanes 0-6 at least must call it, with
+// the same arguments): lane k takes the candidate L = 2^k, its tile count,
+// chunk count and chunk length in parallel, a ballot picks the fewest lanes
+// that satisfy both conditions (else 64) and that lane's chunk length is
+// read back.  Every value is the one plan_split computes; only the serial
+// search is gone.
+__device__ inline void plan_split_wave(const SweepArgs& a, int32_t na, int64_t c_act,
+                                       int32_t* L_out, int32_t* ti_out, int64_t* jc_out)
+{
+    const int C = a.n_clusters;
+    const int64_t want = (int64_t)(a.target_lanes / kWG) > 0 ? a.target_lanes / kWG : 1;
+    int64_t s_cap = a.one_chunk ? 1 : (a.n_cmax + kTJ - 1) / kTJ;
+    if (na > 0) {
+        const int64_t buf_cap = div_floor(a.partial_cap, kRows * (int64_t)na);
+        if (buf_cap < s_cap) s_cap = buf_cap > 0 ? buf_cap : 1;
+    }
+    const int64_t per_cluster = div_ceil(na, c_act);
+    const int lane = threadIdx.x & 63;
+    const int k = lane < 7 ? lane : 6;
+    const int32_t Lk = 1 << k;
+    const int64_t ti_k = (int64_t)a.ipl * (kWG / Lk);
+    const int64_t tiles_k = div_ceil_p2(na, ti_k) + (C > 1 ? c_act : 0);
+    const bool ok = k < 6 && tiles_k * s_cap >= want && ti_k <= 2 * per_cluster;
+    const unsigned long long m = __ballot(ok);
+    const int lg = m ? __builtin_ctzll(m) : 6;
+    const int64_t tiles = na > 0 ? tiles_k : 1;
+    int64_t S = div_ceil(want, tiles);
+    if (S > s_cap) S = s_cap;
+    if (S < 1) S = 1;
+    int64_t jc = div_ceil(a.n_cmax, S);
+    const int64_t jmin = (int64_t)Lk * a.min_j_per_lane;
+    if (jc < jmin) jc = jmin;
+    jc = (jc + kTJ - 1) / kTJ * kTJ;
+    const int lo = __builtin_amdgcn_readlane((int)jc, lg);
+    const int hi = __builtin_amdgcn_readlane((int)(jc >> 32), lg);
+    *L_out = 1 << lg;
+    *ti_out = (int32_t)((int64_t)a.ipl * (kWG >> lg));
+    *jc_out = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 __device__ inline int32_t block_exscan(int32_t v, int32_t* total)
 {
     __shared__ int32_t s_w[kWG / 64];
@@ -362,10 +402,11 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in,
     const int C = a.n_clusters;
     if (C == 1) {
         // one system: everything follows from na and n, no scans needed
+        if (tid >= 64) return;
+        int32_t L, ti;
+        int64_t jc;
+        plan_split_wave(a, na, 1, &L, &ti, &jc);
         if (tid == 0) {
-            int32_t L, ti;
-            int64_t jc;
-            plan_split(a, na, 1, &L, &ti, &jc);
             const int32_t tiles = (int32_t)div_ceil_p2(na, ti);
             const int32_t ch = na > 0 ? (int32_t)div_ceil(a.n, jc) : 0;
             a.act_start[0] = 0;
@@ -435,7 +476,7 @@ __device__ inline void plan_body(const SweepArgs& a, int32_t na_in,
     // evaluates it; it depends only on na, c_act and the arguments)
     int32_t L, ti;
     int64_t jc;
-    plan_split(a, na, c_act > 0 ? c_act : 1, &L, &ti, &jc);
+    plan_split_wave(a, na, c_act > 0 ? c_act : 1, &L, &ti, &jc);
 
     // 3. work items per cluster and their offsets (a thread's clusters'
     // item counts kept in registers when it owns at most kPlanPer of them)

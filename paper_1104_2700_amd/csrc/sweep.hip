@@ -820,7 +820,7 @@ sweep_kernel(SweepArgs a)
         __shared__ int32_t s_idx[kFusedSelMax];
         na = select_in_lds(a.pred_t, a.sel_dt, a.n, a.sel_T_end, s_idx, &Tpred);
         int32_t L_, ti_;
-        plan_split(a, na, 1, &L_, &ti_, &jc);
+        plan_split_wave(a, na, 1, &L_, &ti_, &jc);
         L = L_;
         ti = ti_;
         s_max = na > 0 ? (int)div_ceil(a.n, jc) : 0;
