@@ -49,6 +49,17 @@ FLOPS_ALGO = 42                      # per interaction, operation count
 PEAK_FP64 = 78.6e12                  # MI355X vector FP64, FLOP/s
 PEAK_FP32 = 157.3e12                 # MI355X vector FP32 (packed), FLOP/s
 PEAK_FP32_UNPACKED = 78.6e12         # FP32 as issued by this build
+# The paper's own throughput, quoted as context with its hardware (Section 5,
+# Table 4, Turbo Boost on: AVX on an Intel Core i7-2600 at N = 16K, the
+# largest N it measures; it has no figure at N = 64K).
+PAPER_FIGURES = {
+    "hardware": "Intel Core i7-2600 (Sandy Bridge, 4 cores, 3.4 GHz), AVX, CPU",
+    "n": 16384,
+    "gflops_60_1core_1proc": 20.5,
+    "gflops_60_4cores_8procs": 90.9,
+    "interactions_per_s_4cores_8procs": 90.9e9 / FLOPS_PAPER,
+    "source": "Section 5, Table 4, Turbo Boost on",
+}
 METRIC = ("force+jerk interactions/s & GFLOPS (N=65536); mixed vs FP64 at "
           "≤1e-6 rel err")
 
@@ -264,6 +275,7 @@ def main():
             "frac_vs_fp64_or_unpacked_fp32_peak": achieved / PEAK_FP64,
         },
         "cpu_baseline": cpu,
+        "paper_figures": PAPER_FIGURES,
     }
     if "fp64" in results and head != "fp64":
         f = results["fp64"]
