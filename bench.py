@@ -23,7 +23,9 @@ interaction (count of the operations in the force, jerk and potential
 equations, FMA = 2); the whole force call (plan, sweep, reduce/refine) is
 reported beside it.  Both FP32 difference forms of the mixed sweep (cast and
 split hi/lo) are timed and checked.  The cpu_baseline entry times the FP64
-CPU oracle on a bounded sample of active particles of the same state.
+CPU oracle on a bounded sample of active particles of the same state.  The
+batched entry sweeps the 256-cluster ensemble with every particle active in
+one launch, FP64 against mixed, as a fraction of the vector peaks.
 """
 from __future__ import annotations
 
@@ -83,6 +85,8 @@ def parse():
                     help="autotuner cache: loaded if it has this size, else written")
     ap.add_argument("--retune", action="store_true",
                     help="autotune even when the committed counter summary names a shape")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-cluster ensemble sweep")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -219,6 +223,10 @@ def main():
                 "acc_n_above_1e-6": int((ea > 1e-6).sum()),
                 "pot_rel_max": float(ep.max())}
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(ctx, H, inputs, max(10, args.steps), not args.no_autotune)
+
     cpu = None
     accuracy = {}
     if not args.no_cpu:
@@ -277,6 +285,8 @@ def main():
         "cpu_baseline": cpu,
         "paper_figures": PAPER_FIGURES,
     }
+    if batched is not None:
+        out["batched"] = batched
     if "fp64" in results and head != "fp64":
         f = results["fp64"]
         out["fp64_vs_mixed"] = {
@@ -287,6 +297,66 @@ def main():
                 FLOPS_ALGO * N * N / (f["force_ms"]["sweep"] * 1e-3) / PEAK_FP64,
         }
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(ctx, H, inputs, reps, autotune):
+    """The batched workload: the 256-cluster ensemble (N_c log-uniform in
+    [256, 8192], eps_c = 4/N_c; 673 038 particles) with every particle
+    active, swept in one persistent launch over all clusters (each cluster is
+    its own system: Section 3.3's sweep per cluster, no pair across them).
+    Timed in FP64 and in mixed precision twice: with the library's default
+    policy, which sweeps systems below 32768 particles with the FP64 kernel,
+    and with that rule off, so that every cluster is swept in FP32 (near
+    field and refinement kept).  The launch shapes are autotuned for this
+    workload (untimed); HIP events on the launch stream time the sweep
+    kernels and the whole force call, averaged over ``reps`` calls."""
+    import torch
+    x, v, m, off, eps = inputs.ensemble()
+    n = int(off[-1])
+    cl = H.Clusters(off, eps ** 2)
+    s = H.State(x, v, m, TB)
+    s.xp.copy_(s.x)
+    s.vp.copy_(s.v)
+    sizes = np.diff(off).astype(np.float64)
+    inter = float((sizes * sizes).sum())
+    near, below = ctx.get_mixed_policy(H.MIXED)
+    rows = (("fp64", H.FP64, below), ("mixed_default_policy", H.MIXED, below),
+            ("mixed_fp32_sweeps", H.MIXED, 0))
+    if autotune:
+        ctx.autotune(s, 0.0, H.FP64, n, clusters=cl)
+        ctx.set_mixed_policy(H.MIXED, near, 0)
+        ctx.autotune(s, 0.0, H.MIXED, n, clusters=cl)
+    out = {"workload": "ensemble_256_clusters_n256_8192_all_active",
+           "n_clusters": int(off.shape[0] - 1), "n_particles": n,
+           "interactions_per_sweep": inter}
+    ref = None
+    for label, prec, fp64_below in rows:
+        ctx.set_mixed_policy(H.MIXED, near, fp64_below)
+        a, j, p, _ = ctx.force_jerk_timed(s, None, 0.0, prec, reps=2, clusters=cl)
+        a, j, p, ph = ctx.force_jerk_timed(s, None, 0.0, prec, reps=reps, acc=a, jerk=j,
+                                           pot=p, clusters=cl)
+        torch.cuda.synchronize()
+        peak = PEAK_FP64 if label != "mixed_fp32_sweeps" else PEAK_FP32
+        row = {"force_call_interactions_per_s": inter / (ph["total"] * 1e-3),
+               "sweep_kernel_interactions_per_s": inter / (ph["sweep"] * 1e-3),
+               "gflops_60": FLOPS_PAPER * inter / (ph["total"] * 1e-3) / 1e9,
+               "sweep_frac_of_peak": FLOPS_ALGO * inter / (ph["sweep"] * 1e-3) / peak,
+               "peak": "fp64" if peak == PEAK_FP64 else "fp32",
+               "force_ms": ph, "tuning": ctx.get_tuning(prec).as_dict()}
+        A, J, P = a.cpu().numpy(), j.cpu().numpy(), p.cpu().numpy()
+        if ref is None:
+            ref = (A, J, P)
+        else:
+            A0, J0, _ = ref
+            ea = np.linalg.norm(A - A0, axis=0) / np.linalg.norm(A0, axis=0)
+            ej = np.linalg.norm(J - J0, axis=0) / np.linalg.norm(J0, axis=0)
+            row["vs_fp64_sweep"] = {"acc_rel_max": float(ea.max()),
+                                    "jerk_rel_max": float(ej.max()),
+                                    "acc_n_above_1e-6": int((ea > 1e-6).sum()),
+                                    "jerk_n_above_1e-6": int((ej > 1e-6).sum())}
+        out[label] = row
+    ctx.set_mixed_policy(H.MIXED, near, below)
+    return out
 
 
 def profiled_counters(_unused=None):
