@@ -86,7 +86,8 @@ def parse():
     ap.add_argument("--retune", action="store_true",
                     help="autotune even when the committed counter summary names a shape")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 256-cluster ensemble sweep")
+                    help="skip the 256-cluster ensemble sweep (it runs only when "
+                         "--precisions holds both fp64 and mixed)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -224,7 +225,7 @@ def main():
                 "pot_rel_max": float(ep.max())}
 
     batched = None
-    if not args.no_batched:
+    if not args.no_batched and "fp64" in results and "mixed" in results:
         batched = batched_leg(ctx, H, inputs, max(10, args.steps), not args.no_autotune)
 
     cpu = None
